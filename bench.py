@@ -1,0 +1,198 @@
+"""Benchmark of the DGSEM hot path on one MI355X.
+
+Default workload: Taylor-Green vortex (Re 1600, Ma 0.1, Version II) on a curved
+periodic 24^3 hexahedral mesh, N = 7 Gauss nodes (7,077,888 DOF), Roe + BR1,
+LSERK4-5, FP64.  A step is one RK step: five evaluations of the whole operator
+(traces, BR1 lifting, face fluxes, volume and surface integrals, Jacobian)
+and the stage updates.  value = DOF * 5 * steps / wall time (DOF counts
+nodes, as the paper's PID does); PID = 1 / value at one GPU.
+
+Also reported on the same line: the per-kernel roofline of the dominant
+kernel (HIP events on the solver's stream), the mixed-precision form on the
+32^3 mesh, the p50/p99 latency of whole solves, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def algorithmic_bytes_per_dof(N: int, mixed: bool):
+    """minimum HBM bytes per DOF and stage of the two sweeps BR1 forces:
+    sweep 1 (lifting) reads U, Ja, 1/J and the neighbours' U traces and writes
+    g traces; sweep 2 reads U, Ja, 1/J, U and g traces and du, writes du, U and
+    the next U traces.  f = 6/(N+1) face slots per DOF."""
+    f = 6.0 / (N + 1)
+    if not mixed:
+        lift = 8 * (15 + 17 * f)
+        rhs = 8 * (30 + 22 * f)
+    else:  # state, RK register and U re-read in FP64; metrics, traces in FP32
+        lift = 8 * 5 + 4 * (10 + 17 * f)
+        rhs = 8 * 20 + 4 * (10 + 22 * f)
+    return lift, rhs
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2404_12703_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name):
+    """HBM traffic per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs, valid only for the kernel sources they were taken on"""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
+def time_solver(P, wl, steps, warmup, profile_pass=True):
+    import torch
+    s = P.Solver(wl.params, wl.mesh)
+    s.set_state(wl.U0, 0.0)
+    dt = s.stable_dt(0.9, 0.9)
+    s.advance(warmup, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(steps, dt)
+    s.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = None
+    if profile_pass:
+        s.profile(True)
+        s.advance(steps, dt)
+        prof = s.profile_read()
+        s.profile(False)
+    return s, dt, el, prof
+
+
+def latency(P, wl, steps, repeats):
+    import torch
+    s = P.Solver(wl.params, wl.mesh)
+    s.set_state(wl.U0, 0.0)
+    dt = s.stable_dt(0.9, 0.9)
+    U0 = torch.from_numpy(wl.U0).cuda()
+    out = torch.empty_like(U0)
+    lat = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_state(U0, 0.0)
+        s.advance(steps, dt)
+        s.state_into(out)
+        s.synchronize()
+        lat.append(time.perf_counter() - t0)
+    return np.percentile(lat, 50), np.percentile(lat, 99)
+
+
+def cpu_baseline(wl, seconds_budget=30.0):
+    """the FP64 oracle, untuned, on the host cores: one full RK step (five
+    operator evaluations) of the same workload"""
+    import oracle as O
+    o = O.Oracle(wl.params, wl.mesh)
+    dt = o.stable_dt(wl.U0)
+    t0 = time.perf_counter()
+    o.advance(wl.U0, dt, 1)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=wl.dof * 5 / el, unit="DOF*stage/s", cores=cores, kind="oracle",
+                sample=f"1 RK step (5 operator evaluations) of the full {wl.name} workload, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--K", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip mixed precision and latency")
+    ap.add_argument("--only-main", action="store_true", help="time the main workload only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2404_12703_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.tgv_workload(K=args.K, N=7, steps=args.steps)
+    N = 7
+    s, dt, el, prof = time_solver(P, wl, args.steps, args.warmup, profile_pass=not args.only_main)
+    value = wl.dof * 5 * args.steps / el
+    line = {
+        "metric": "DOF*RK-stage updates/s (PID = 1/value) FP64 on 1 GPU; p50/p99 solve latency",
+        "value": value, "unit": "DOF*stage/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"tgv_re1600_ma0.1_curved_{args.K}^3_N7_gauss_roe_br1_lserk45_fp64",
+                   "elements": wl.mesh.n_elems, "N": N, "dof": wl.dof, "dt": dt},
+        "pid_s": 1.0 / value,
+    }
+    if prof is not None:
+        lift_b, rhs_b = algorithmic_bytes_per_dof(N, False)
+        ms_rhs, n_rhs = prof["rhs"]
+        ms_lift, n_lift = prof["lift"]
+        t_rhs, t_lift = ms_rhs / n_rhs * 1e-3, ms_lift / n_lift * 1e-3
+        ach = rhs_b * wl.dof / t_rhs / 1e9
+        tr = load_traffic("traffic_k_rhs_tgv24_n7_fp64.json")
+        line["roofline"] = {"kernel": "k_rhs (VolInt+FillFlux+SurfInt+ApplyJac+LSERK update+ProlongToFace)",
+                            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS,
+                            "traffic": (tr["bytes_per_launch"] if tr else None),
+                            "alg_bytes_per_launch": rhs_b * wl.dof, "avg_launch_ms": t_rhs * 1e3}
+        lift_ach = lift_b * wl.dof / t_lift / 1e9
+        line["kernels"] = {
+            "k_rhs": {"avg_ms": t_rhs * 1e3, "launches": n_rhs, "alg_GBs": ach},
+            "k_lift": {"avg_ms": t_lift * 1e3, "launches": n_lift, "alg_GBs": lift_ach},
+        }
+        step_alg = (lift_b + rhs_b) * wl.dof * 5 * args.steps / el / 1e9
+        line["whole_step_alg_GBs"] = step_alg
+        line["whole_step_hbm_frac"] = step_alg / HBM_PEAK_GBS
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_extras and not args.only_main:
+        # mixed precision: FP32 fluxes/contractions, FP64 state and RK, on the 32^3 mesh
+        wm = W.tgv_workload(K=32, N=7, steps=20, precision=1)
+        sm, dtm, elm, profm = time_solver(P, wm, 20, 2, profile_pass=False)
+        wd = W.tgv_workload(K=32, N=7, steps=20, precision=0)
+        sd, dtd, eld, _ = time_solver(P, wd, 20, 2, profile_pass=False)
+        line["mixed_tgv32"] = {"value_mixed": wm.dof * 5 * 20 / elm, "value_fp64": wd.dof * 5 * 20 / eld,
+                               "speedup": eld / elm, "steps": 20, "dof": wm.dof}
+        del sm, sd
+        torch.cuda.empty_cache()
+        p50, p99 = latency(P, W.tgv_workload(K=args.K, N=7, steps=args.steps), args.steps, 5)
+        line["latency_s"] = {"p50": p50, "p99": p99, "solve": f"set_state + {args.steps} steps + get_state",
+                             "repeats": 5}
+    if not args.no_cpu and not args.only_main:
+        line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+// physics.h -- pointwise physics of the compressible Navier-Stokes equations
+// for the HIP kernels: ConsToPrim, advective and viscous fluxes, Riemann
+// solvers.  Paper (GALAEXI, arXiv 2404.12703): Sec. 2.1 Eqs. nse, eos_p, eos_T;
+// Table tab:dg_routines (ConsToPrim, FillFlux); App. A (FillFlux).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dg {
+
+// prim = (rho, u, v, w, p, T) from U = (rho, rho u, rho v, rho w, rho e)
+template <typename real>
+__device__ __forceinline__ void cons2prim(const real *U, real gamma, real Rgas, real *P) {
+  const real rho = U[0];
+  const real u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
+  const real p = (gamma - real(1)) * (U[4] - real(0.5) * rho * (u * u + v * v + w * w));
+  P[0] = rho;
+  P[1] = u;
+  P[2] = v;
+  P[3] = w;
+  P[4] = p;
+  P[5] = p / (rho * Rgas);
+}
+
+// advective flux in Cartesian direction d (compile-time)
+template <int d, typename real>
+__device__ __forceinline__ void flux_adv(const real *U, const real *P, real *F) {
+  const real ud = P[1 + d];
+  F[0] = U[1 + d];
+  F[1] = U[1] * ud;
+  F[2] = U[2] * ud;
+  F[3] = U[3] * ud;
+  F[1 + d] += P[4];
+  F[4] = (U[4] + P[4]) * ud;
+}
+
+// viscous flux in direction d from primitives and lifted gradients
+// g[dd*4 + var], var = (u, v, w, T): tau = mu (grad u + grad u^T - 2/3 div u I),
+// energy: tau.u + lambda dT/dx_d.  Enters the total flux as F_adv - F_visc.
+template <int d, typename real>
+__device__ __forceinline__ void flux_visc(const real *P, const real *g, real mu, real lambda, real *F) {
+  const real divu = g[0] + g[5] + g[10];
+  real tau[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    tau[a] = mu * (g[d * 4 + a] + g[a * 4 + d]);
+    if (a == d) tau[a] -= real(2.0 / 3.0) * mu * divu;
+  }
+  F[0] = real(0);
+  F[1] = tau[0];
+  F[2] = tau[1];
+  F[3] = tau[2];
+  F[4] = tau[0] * P[1] + tau[1] * P[2] + tau[2] * P[3] + lambda * g[d * 4 + 3];
+}
+
+template <typename real>
+__device__ __forceinline__ void flux_normal(const real *U, const real *P, const real *nv, real *F) {
+  real f[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0);
+  flux_adv<0>(U, P, f);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] += f[v] * nv[0];
+  flux_adv<1>(U, P, f);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] += f[v] * nv[1];
+  flux_adv<2>(U, P, f);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] += f[v] * nv[2];
+}
+
+// local Lax-Friedrichs: 1/2 (F_L + F_R).n - 1/2 max(|u.n| + c) (U_R - U_L)
+template <typename real>
+__device__ __forceinline__ void riemann_llf(const real *UL, const real *PL, const real *UR, const real *PR,
+                                            const real *nv, real gamma, real *F) {
+  real FL[5], FR[5];
+  flux_normal(UL, PL, nv, FL);
+  flux_normal(UR, PR, nv, FR);
+  const real cL = sqrt(gamma * PL[4] / PL[0]), cR = sqrt(gamma * PR[4] / PR[0]);
+  const real unL = PL[1] * nv[0] + PL[2] * nv[1] + PL[3] * nv[2];
+  const real unR = PR[1] * nv[0] + PR[2] * nv[1] + PR[3] * nv[2];
+  const real lmax = fmax(fabs(unL) + cL, fabs(unR) + cR);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lmax * (UR[v] - UL[v]);
+}
+
+// Roe's approximate Riemann solver without entropy fix: central flux minus
+// half the sum over the five characteristic waves |lambda_k| a_k r_k at the
+// Roe-averaged state.
+template <typename real>
+__device__ __forceinline__ void riemann_roe(const real *UL, const real *PL, const real *UR, const real *PR,
+                                            const real *nv, real gamma, real *F) {
+  real FL[5], FR[5];
+  flux_normal(UL, PL, nv, FL);
+  flux_normal(UR, PR, nv, FR);
+  const real sL = sqrt(PL[0]), sR = sqrt(PR[0]);
+  const real inv = real(1) / (sL + sR);
+  const real HL = (UL[4] + PL[4]) / PL[0], HR = (UR[4] + PR[4]) / PR[0];
+  real ut[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ut[d] = (sL * PL[1 + d] + sR * PR[1 + d]) * inv;
+  const real Ht = (sL * HL + sR * HR) * inv;
+  const real q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const real c2 = (gamma - real(1)) * (Ht - real(0.5) * q2);
+  const real ct = sqrt(c2);
+  const real rt = sL * sR;
+  const real un = ut[0] * nv[0] + ut[1] * nv[1] + ut[2] * nv[2];
+  real du[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) du[d] = PR[1 + d] - PL[1 + d];
+  const real dun = du[0] * nv[0] + du[1] * nv[1] + du[2] * nv[2];
+  const real drho = PR[0] - PL[0], dp = PR[4] - PL[4];
+  const real a1 = (dp - rt * ct * dun) / (real(2) * c2);
+  const real a2 = drho - dp / c2;
+  const real a3 = (dp + rt * ct * dun) / (real(2) * c2);
+  const real l1 = fabs(un - ct) * a1, l2 = fabs(un) * a2, l3 = fabs(un + ct) * a3;
+  const real ls = fabs(un) * rt;
+  real dut[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) dut[d] = du[d] - dun * nv[d];
+  const real udut = ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2];
+  real Dis[5];
+  Dis[0] = l1 + l2 + l3;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    Dis[1 + d] = l1 * (ut[d] - ct * nv[d]) + l2 * ut[d] + ls * dut[d] + l3 * (ut[d] + ct * nv[d]);
+  Dis[4] = l1 * (Ht - un * ct) + l2 * real(0.5) * q2 + ls * udut + l3 * (Ht + un * ct);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * Dis[v];
+}
+
+}  // namespace dg

@@ -1,0 +1,488 @@
+// solver.cpp -- the C ABI of one solve: workspace layout, set-up upload, the
+// RK stage driver and the small reductions.  Every step of the time
+// derivative runs in the HIP kernels of kernels.hip.
+//
+// Paper (GALAEXI, arXiv 2404.12703): the time-stepping loop of Sec. 2.2
+// ("Time integration": Carpenter-Kennedy five-stage fourth-order 2N-storage
+// scheme) around the DG operator of Eq. dgsem; all of it on the device with
+// no host transfers during time stepping (Sec. 3, design principles).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+#include "solver_impl.h"
+
+namespace dg {
+
+thread_local std::string g_last_error;
+
+dg_status fail(dg_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Carpenter-Kennedy (1994) five-stage fourth-order 2N-storage coefficients
+const double RK_A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double RK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+const double RK_C[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                        2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+dg_status check_params(const dg_params *p) {
+  if (!p) return fail(DG_EINVAL, "params is NULL");
+  if (p->abi_version != DG_ABI_VERSION) return fail(DG_EINVAL, "abi_version mismatch");
+  if (p->N < 1 || p->N > N_MAX) return fail(DG_EINVAL, "N must be in 1..9");
+  if (p->nodes != 0 && p->nodes != 1) return fail(DG_EINVAL, "nodes must be 0 (Gauss) or 1 (Lobatto)");
+  if (p->riemann != 0 && p->riemann != 1) return fail(DG_EINVAL, "riemann must be 0 (LLF) or 1 (Roe)");
+  if (p->precision != 0 && p->precision != 1) return fail(DG_EINVAL, "precision must be 0 or 1");
+  if (p->shock_capturing && (p->nodes != 1 || p->N < 2))
+    return fail(DG_EINVAL, "shock capturing needs Gauss-Lobatto nodes and N >= 2");
+  if (!(p->gamma > 1.0) || !(p->R > 0.0) || !(p->Pr > 0.0) || !(p->mu >= 0.0))
+    return fail(DG_EINVAL, "need gamma > 1, R > 0, Pr > 0, mu >= 0");
+  if (p->shock_capturing && !(p->alpha_max >= 0.0 && p->alpha_max <= 1.0 && p->alpha_min >= 0.0 && p->ind_a > 0.0))
+    return fail(DG_EINVAL, "bad indicator parameters");
+  return DG_OK;
+}
+
+namespace {
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+Layout make_layout(const dg_params &p, int64_t E) {
+  Layout L;
+  const int n = p.N + 1;
+  const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
+  const size_t rs = p.precision ? sizeof(float) : sizeof(double);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.U = take(5 * E * n3 * 8);
+  L.dU = take(5 * E * n3 * 8);
+  L.Ja = take(9 * E * n3 * rs);
+  L.invJ = take(E * n3 * rs);
+  L.NS = take(3 * E * 6 * n2 * rs);
+  L.Utr0 = take(5 * E * 6 * n2 * rs);
+  L.Utr1 = take(5 * E * 6 * n2 * rs);
+  L.Gtr = p.viscous ? take(12 * E * 6 * n2 * rs) : SIZE_MAX;
+  L.G = p.viscous ? take(12 * E * n3 * rs) : SIZE_MAX;
+  L.conn = take(6 * E * sizeof(int2));
+  L.Xs = p.source ? take(3 * E * n3 * 8) : SIZE_MAX;
+  L.basis = take(BasisOffsets(n).total * rs);
+  L.alpha = take(E * rs);
+  L.alpha_in = take(E * rs);
+  L.scratch = take(kRedBlocks * 8 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+template <typename real>
+static void fill_view(dg_solver *s, View<real> &v) {
+  char *ws = (char *)s->ws;
+  const Layout &L = s->L;
+  auto at = [&](size_t off) -> char * { return off == SIZE_MAX ? nullptr : ws + off; };
+  v.E = s->E;
+  v.U = (double *)at(L.U);
+  v.dU = (double *)at(L.dU);
+  v.R = nullptr;
+  v.Ja = (const real *)at(L.Ja);
+  v.invJ = (const real *)at(L.invJ);
+  v.NS = (const real *)at(L.NS);
+  v.Utr0 = (real *)at(L.Utr0);
+  v.Utr1 = (real *)at(L.Utr1);
+  v.Gtr = (real *)at(L.Gtr);
+  v.G = (real *)at(L.G);
+  v.conn = (const int2 *)at(L.conn);
+  v.Xs = (const double *)at(L.Xs);
+  v.basis = (const real *)at(L.basis);
+  v.alpha = (real *)at(L.alpha);
+  v.alpha_in = nullptr;
+  const dg_params &p = s->p;
+  v.gamma = (real)p.gamma;
+  v.Rgas = (real)p.R;
+  v.mu = (real)p.mu;
+  v.lambda = (real)(p.gamma * p.R * p.mu / ((p.gamma - 1.0) * p.Pr));
+  v.Pr = p.Pr;
+  v.t = 0.0;
+  v.dt = 0.0;
+  v.rkA = 0.0;
+  v.rkB = 0.0;
+  v.cur = 0;
+  v.viscous = p.viscous;
+  v.riemann = p.riemann;
+  v.source = p.source;
+  v.shock = p.shock_capturing;
+  v.ind_a = (real)p.ind_a;
+  v.ind_c = (real)p.ind_c;
+  v.ind_s = (real)p.ind_s;
+  v.alpha_min = (real)p.alpha_min;
+  v.alpha_max = (real)p.alpha_max;
+  v.ind_T = (real)(p.ind_a * std::pow(10.0, -p.ind_c * std::pow(p.N + 1.0, 0.25)));
+}
+
+// upload a host FP64 array into device memory of the solve's arithmetic type
+static hipError_t upload_real(dg_solver *s, size_t off, const std::vector<double> &h) {
+  char *dst = (char *)s->ws + off;
+  if (!s->mixed) return hipMemcpyAsync(dst, h.data(), h.size() * 8, hipMemcpyHostToDevice, s->st);
+  std::vector<float> f(h.size());
+  for (size_t i = 0; i < h.size(); ++i) f[i] = (float)h[i];
+  hipError_t e = hipMemcpyAsync(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);  // f goes out of scope
+  return e;
+}
+
+dg_status device_error(dg_solver *s, hipError_t e, const char *what) {
+  if (s) s->broken = true;
+  return fail(DG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// enqueue one kernel for this solve (records profiling events when enabled)
+template <typename real>
+static hipError_t run_kernel(dg_solver *s, Kernel k, int mode, const View<real> &v) {
+  int blocks = blocks_per_elements(s->p.N, s->E);
+  if (s->prof_on) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s->st);
+    hipError_t e = launch<real>(k, s->p.N, mode, nullptr, nullptr, 0, blocks, v, s->st);
+    (void)hipEventRecord(b, s->st);
+    s->prof_events.push_back({(int)k, a, b});
+    return e;
+  }
+  return launch<real>(k, s->p.N, mode, nullptr, nullptr, 0, blocks, v, s->st);
+}
+
+template <typename real>
+static View<real> &view_of(dg_solver *s);
+template <>
+View<double> &view_of<double>(dg_solver *s) {
+  return s->vd;
+}
+template <>
+View<float> &view_of<float>(dg_solver *s) {
+  return s->vf;
+}
+
+// one evaluation of the operator: traces (if stale), lifting, time derivative.
+// mode 0: stage update with (t, dt, A, B); mode 1: write R to Rout.
+template <typename real>
+static hipError_t stage(dg_solver *s, int mode, double t, double dt, double A, double B, double *Rout) {
+  View<real> &v = view_of<real>(s);
+  v.t = t;
+  v.dt = dt;
+  v.rkA = A;
+  v.rkB = B;
+  v.cur = s->cur;
+  v.R = Rout;
+  hipError_t e = hipSuccess;
+  if (!s->traces_valid) {
+    e = run_kernel<real>(s, K_TRACE, 0, v);
+    if (e != hipSuccess) return e;
+    s->traces_valid = true;
+  }
+  if (s->p.viscous) {
+    e = run_kernel<real>(s, K_LIFT, 0, v);
+    if (e != hipSuccess) return e;
+  }
+  e = run_kernel<real>(s, K_RHS, mode, v);
+  if (e != hipSuccess) return e;
+  if (mode == 0) s->cur ^= 1;
+  return hipSuccess;
+}
+
+template <typename real>
+static hipError_t advance_impl(dg_solver *s, int nsteps, double dt) {
+  for (int st = 0; st < nsteps; ++st) {
+    const double t0 = s->t;
+    for (int k = 0; k < 5; ++k) {
+      hipError_t e = stage<real>(s, 0, t0 + RK_C[k] * dt, dt, RK_A[k], RK_B[k], nullptr);
+      if (e != hipSuccess) return e;
+    }
+    s->t = t0 + dt;
+  }
+  return hipSuccess;
+}
+
+hipError_t solver_advance(dg_solver *s, int nsteps, double dt) {
+  return s->mixed ? advance_impl<float>(s, nsteps, dt) : advance_impl<double>(s, nsteps, dt);
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+extern "C" {
+
+int32_t dg_abi_version(void) { return DG_ABI_VERSION; }
+
+const char *dg_last_error(void) { return g_last_error.c_str(); }
+
+dg_status dg_workspace_bytes(const dg_params *p, int64_t n_elems, size_t *bytes) {
+  dg_status rc = check_params(p);
+  if (rc) return rc;
+  if (n_elems < 1 || n_elems * 6 >= INT32_MAX) return fail(DG_EINVAL, "n_elems out of range");
+  if (!bytes) return fail(DG_EINVAL, "bytes is NULL");
+  *bytes = make_layout(*p, n_elems).total;
+  return DG_OK;
+}
+
+dg_status dg_create(const dg_params *p, const dg_mesh *m, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                    dg_solver **out) {
+  g_last_error.clear();
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  dg_status rc = check_params(p);
+  if (rc) return rc;
+  if (!m || !m->x_geo || !m->nbr_elem || !m->nbr_face || !m->nbr_orient) return fail(DG_EINVAL, "mesh arrays missing");
+  if (m->n_elems < 1 || m->n_elems * 6 >= INT32_MAX) return fail(DG_EINVAL, "n_elems out of range");
+  if (m->n_geo < 1 || m->n_geo > p->N) return fail(DG_EINVAL, "n_geo must be in 1..N");
+  if (!d_workspace) return fail(DG_EINVAL, "workspace is NULL");
+  if ((uintptr_t)d_workspace % 256) return fail(DG_EINVAL, "workspace must be 256-byte aligned");
+  Layout L = make_layout(*p, m->n_elems);
+  if (ws_bytes < L.total)
+    return fail(DG_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  std::unique_ptr<dg_solver> s(new (std::nothrow) dg_solver());
+  if (!s) return fail(DG_ENOMEM, "host allocation failed");
+  s->p = *p;
+  s->E = m->n_elems;
+  s->ws = d_workspace;
+  s->ws_bytes = ws_bytes;
+  s->L = L;
+  s->st = (hipStream_t)hip_stream;
+  s->mixed = p->precision == 1;
+
+  Basis b = make_basis(p->N, p->nodes);
+  Geometry g;
+  std::string err;
+  rc = build_geometry(b, *m, g, err);
+  if (rc) return fail(rc, err);
+  std::vector<double> invJ(g.J.size());
+  for (size_t i = 0; i < g.J.size(); ++i) invJ[i] = 1.0 / g.J[i];
+
+  fill_view(s.get(), s->vd);
+  fill_view(s.get(), s->vf);
+  hipError_t e = hipMemsetAsync(s->ws, 0, L.total, s->st);
+  if (e == hipSuccess) e = upload_real(s.get(), L.Ja, g.Ja);
+  if (e == hipSuccess) e = upload_real(s.get(), L.invJ, invJ);
+  if (e == hipSuccess) e = upload_real(s.get(), L.NS, g.NS);
+  if (e == hipSuccess) e = upload_real(s.get(), L.basis, basis_block(b));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((char *)s->ws + L.conn, g.conn.data(), g.conn.size() * sizeof(int2), hipMemcpyHostToDevice,
+                       s->st);
+  if (e == hipSuccess && p->source)
+    e = hipMemcpyAsync((char *)s->ws + L.Xs, g.Xs.data(), g.Xs.size() * 8, hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);  // host vectors go out of scope
+  if (e != hipSuccess) return device_error(nullptr, e, "dg_create upload");
+  s->t = 0.0;
+  s->cur = 0;
+  s->traces_valid = false;
+  *out = s.release();
+  return DG_OK;
+}
+
+void dg_destroy(dg_solver *s) {
+  if (!s) return;
+  for (auto &pe : s->prof_events) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  delete s;
+}
+
+#define CHECK_SOLVER(s)                                                         \
+  do {                                                                          \
+    if (!(s)) return fail(DG_EINVAL, "solver is NULL");                         \
+    if ((s)->broken) return fail(DG_ESTATE, "solver unusable after a device error"); \
+  } while (0)
+
+dg_status dg_set_state(dg_solver *s, const double *U, int32_t on_device, double t) {
+  CHECK_SOLVER(s);
+  if (!U) return fail(DG_EINVAL, "U is NULL");
+  size_t bytes = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1) * 8;
+  hipError_t e = hipMemcpyAsync((char *)s->ws + s->L.U, U, bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_set_state");
+  s->t = t;
+  s->traces_valid = false;
+  return DG_OK;
+}
+
+dg_status dg_get_state(dg_solver *s, double *U, int32_t on_device, double *t) {
+  CHECK_SOLVER(s);
+  if (!U) return fail(DG_EINVAL, "U is NULL");
+  size_t bytes = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1) * 8;
+  hipError_t e = hipMemcpyAsync(U, (char *)s->ws + s->L.U, bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_get_state");
+  if (t) *t = s->t;
+  return DG_OK;
+}
+
+dg_status dg_advance(dg_solver *s, int32_t n_steps, double dt) {
+  CHECK_SOLVER(s);
+  if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "need n_steps >= 0 and dt > 0");
+  hipError_t e = solver_advance(s, n_steps, dt);
+  if (e != hipSuccess) return device_error(s, e, "dg_advance");
+  if (s->p.check_finite) {
+    int *flags = (int *)((char *)s->ws + s->L.scratch);
+    size_t count = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1);
+    e = launch_finite((const double *)((char *)s->ws + s->L.U), count, flags, s->st);
+    std::vector<int> h(256);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), flags, 256 * sizeof(int), hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) return device_error(s, e, "dg_advance finiteness check");
+    for (int x : h)
+      if (x) return fail(DG_ENONFINITE, "state is not finite after dg_advance");
+  }
+  return DG_OK;
+}
+
+dg_status dg_rhs(dg_solver *s, double t, double *Ut, int32_t on_device) {
+  CHECK_SOLVER(s);
+  if (!Ut) return fail(DG_EINVAL, "Ut is NULL");
+  // a host destination is staged through the RK register, which carries no
+  // information between steps (A_1 = 0 restarts it)
+  double *dst = on_device ? Ut : (double *)((char *)s->ws + s->L.dU);
+  hipError_t e = s->mixed ? stage<float>(s, 1, t, 0.0, 0.0, 0.0, dst) : stage<double>(s, 1, t, 0.0, 0.0, 0.0, dst);
+  if (e == hipSuccess && !on_device) {
+    size_t bytes = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1) * 8;
+    e = hipMemcpyAsync(Ut, dst, bytes, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  }
+  if (e != hipSuccess) return device_error(s, e, "dg_rhs");
+  return DG_OK;
+}
+
+dg_status dg_stable_dt(dg_solver *s, double cfl, double dfl, double *dt) {
+  CHECK_SOLVER(s);
+  if (!dt || !(cfl > 0) || !(dfl > 0)) return fail(DG_EINVAL, "bad arguments");
+  double *scr = (double *)((char *)s->ws + s->L.scratch);
+  hipError_t e = s->mixed ? launch_dt<float>(s->p.N, s->vf, scr, kRedBlocks, s->st)
+                          : launch_dt<double>(s->p.N, s->vd, scr, kRedBlocks, s->st);
+  std::vector<double> h(2 * kRedBlocks);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), scr, h.size() * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_stable_dt");
+  double a = 1e300, v = 1e300;
+  for (int b = 0; b < kRedBlocks; ++b) {
+    a = std::min(a, h[2 * b]);
+    v = std::min(v, h[2 * b + 1]);
+  }
+  if (!(a < 1e299)) return fail(DG_ENONFINITE, "no finite time step (state not finite?)");
+  *dt = std::min(cfl * a, dfl * v);
+  return DG_OK;
+}
+
+dg_status dg_integrals(dg_solver *s, double out[7]) {
+  CHECK_SOLVER(s);
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  double *scr = (double *)((char *)s->ws + s->L.scratch);
+  hipError_t e = s->mixed ? launch_integrals<float>(s->p.N, s->vf, scr, kRedBlocks, s->st)
+                          : launch_integrals<double>(s->p.N, s->vd, scr, kRedBlocks, s->st);
+  std::vector<double> h(7 * kRedBlocks);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), scr, h.size() * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_integrals");
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < kRedBlocks; ++b)
+    for (int c = 0; c < 7; ++c) acc[c] += h[7 * b + c];
+  for (int c = 0; c < 5; ++c) out[c] = acc[c];
+  out[5] = acc[5] / acc[6];
+  out[6] = acc[6];
+  return DG_OK;
+}
+
+dg_status dg_alpha(dg_solver *s, double *alpha_host) {
+  CHECK_SOLVER(s);
+  if (!alpha_host) return fail(DG_EINVAL, "alpha is NULL");
+  const size_t E = s->E;
+  hipError_t e;
+  if (s->mixed) {
+    std::vector<float> f(E);
+    e = hipMemcpyAsync(f.data(), (char *)s->ws + s->L.alpha, E * 4, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    for (size_t i = 0; i < E; ++i) alpha_host[i] = f[i];
+  } else {
+    e = hipMemcpyAsync(alpha_host, (char *)s->ws + s->L.alpha, E * 8, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  }
+  if (e != hipSuccess) return device_error(s, e, "dg_alpha");
+  return DG_OK;
+}
+
+dg_status dg_set_alpha(dg_solver *s, const double *alpha_host) {
+  CHECK_SOLVER(s);
+  if (!alpha_host) {
+    s->vd.alpha_in = nullptr;
+    s->vf.alpha_in = nullptr;
+    return DG_OK;
+  }
+  std::vector<double> a(alpha_host, alpha_host + s->E);
+  for (double x : a)
+    if (!(x >= 0.0 && x <= 1.0)) return fail(DG_EINVAL, "alpha must lie in [0, 1]");
+  hipError_t e = upload_real(s, s->L.alpha_in, a);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_set_alpha");
+  s->vd.alpha_in = (const double *)((char *)s->ws + s->L.alpha_in);
+  s->vf.alpha_in = (const float *)((char *)s->ws + s->L.alpha_in);
+  return DG_OK;
+}
+
+dg_status dg_synchronize(dg_solver *s) {
+  CHECK_SOLVER(s);
+  hipError_t e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_synchronize");
+  return DG_OK;
+}
+
+dg_status dg_profile_enable(dg_solver *s, int32_t on) {
+  CHECK_SOLVER(s);
+  s->prof_on = on != 0;
+  for (auto &pe : s->prof_events) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  s->prof_events.clear();
+  return DG_OK;
+}
+
+dg_status dg_profile_read(dg_solver *s, int32_t n, double *ms, int64_t *launches) {
+  CHECK_SOLVER(s);
+  if (n < 0 || (n > 0 && (!ms || !launches))) return fail(DG_EINVAL, "bad arguments");
+  hipError_t e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_profile_read");
+  for (int k = 0; k < n; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto &pe : s->prof_events) {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, pe.a, pe.b);
+    if (pe.kernel < n) {
+      ms[pe.kernel] += t;
+      launches[pe.kernel] += 1;
+    }
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  s->prof_events.clear();
+  return DG_OK;
+}
+
+}  // extern "C"

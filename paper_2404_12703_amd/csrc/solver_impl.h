@@ -1,0 +1,49 @@
+// solver_impl.h -- the solver object behind the opaque dg_solver handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+constexpr int kRedBlocks = 1024;  // blocks of the reduction kernels
+
+// byte offsets of every array inside the caller's workspace (SIZE_MAX: absent)
+struct Layout {
+  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Gtr, G, conn, Xs, basis, alpha, alpha_in, scratch, total;
+};
+
+Layout make_layout(const dg_params &p, int64_t E);
+dg_status check_params(const dg_params *p);
+dg_status fail(dg_status code, const std::string &msg);
+
+extern const double RK_A[5], RK_B[5], RK_C[5];
+
+struct ProfEvent {
+  int kernel;
+  hipEvent_t a, b;
+};
+
+}  // namespace dg
+
+struct dg_solver {
+  dg_params p{};
+  int64_t E = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  dg::Layout L{};
+  hipStream_t st = nullptr;
+  bool mixed = false;
+  bool broken = false;
+  dg::View<double> vd{};
+  dg::View<float> vf{};
+  double t = 0.0;
+  int cur = 0;
+  bool traces_valid = false;
+  bool prof_on = false;
+  std::vector<dg::ProfEvent> prof_events;
+};
