@@ -108,6 +108,38 @@ def latency(P, wl, steps, repeats):
     return np.percentile(lat, 50), np.percentile(lat, 99)
 
 
+def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30, max_active=64):
+    """the served stream: nreq seeded requests (K in 4..16, N in {3,5,7},
+    Ma, Re, steps drawn per request) with Poisson arrivals at `load` times the
+    measured throughput, FIFO admission under an HBM budget.  Returns
+    throughput over the makespan and p50/p99 of t_done - t_arrival."""
+    import torch
+    base = W.serving_requests(nreq, seed, rate=1.0)
+    work = [(r["K"] ** 3) * (r["N"] + 1) ** 3 * 5 * r["steps"] for r in base]
+    lam = load * throughput / float(np.mean(work))
+    g = np.random.default_rng(seed + 1000)
+    arrivals = np.cumsum(g.exponential(1.0 / lam, size=nreq))
+    arena = min(budget + (256 << 20), int(torch.cuda.mem_get_info()[0] * 0.8))
+    sv = P.Server(arena_bytes=arena, hbm_budget=budget, max_active=max_active)
+    ids = []
+    for r, ta in zip(base, arrivals):
+        wl = W.request_workload(r, precision=precision)
+        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, r["steps"], -0.9, float(ta)))
+    t0 = time.perf_counter()
+    sv.run(0)
+    makespan = time.perf_counter() - t0
+    lat, ok = [], 0
+    for rid in ids:
+        _, tm = sv.fetch(rid)
+        ok += tm["state"] == P.REQ_DONE
+        lat.append(tm["t_done"] - tm["t_arrival"])
+    sv.close()
+    return dict(requests=nreq, done=ok, load=load, precision=precision,
+                value=float(np.sum(work)) / makespan, unit="DOF*stage/s",
+                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                makespan_s=makespan, budget_GB=budget / 2 ** 30)
+
+
 def cpu_baseline(wl, seconds_budget=30.0):
     """the FP64 oracle, untuned, on the host cores: one full RK step (five
     operator evaluations) of the same workload"""
@@ -129,6 +161,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--K", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the served stream")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed precision and latency")
     ap.add_argument("--only-main", action="store_true", help="time the main workload only (profiling runs)")
     args = ap.parse_args()
@@ -189,6 +222,7 @@ def main():
         p50, p99 = latency(P, W.tgv_workload(K=args.K, N=7, steps=args.steps), args.steps, 5)
         line["latency_s"] = {"p50": p50, "p99": p99, "solve": f"set_state + {args.steps} steps + get_state",
                              "repeats": 5}
+        line["served"] = [served(P, W, args.serve_requests, 0, value, precision=pr) for pr in (0, 1)]
     if not args.no_cpu and not args.only_main:
         line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1))
     print(json.dumps(line), flush=True)

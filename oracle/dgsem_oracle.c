@@ -31,6 +31,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The basis and the metric terms are computed in extended precision (x87
+ * long double) and rounded once to double. */
+typedef long double xr;
+#define XPI 3.141592653589793238462643383279502884L
+
 #define NV 5  /* rho, rho u, rho v, rho w, rho e */
 #define NL 4  /* lifted primitives u, v, w, T    */
 /* position of lifted variable v in prim = (rho, u, v, w, p, T) */
@@ -42,9 +47,7 @@ typedef struct orc {
   double period[3];
   /* 1-D operators on the solution nodes (Sec. 2.2, Eq. dgsem) */
   double *x, *w, *D, *Dhat, *lm, *lp, *lhm, *lhp;
-  /* LGL(N) grid used for the geometry and the metric terms */
-  double *xg, *wg, *Dg;
-  double *Mg2s;  /* [n][n] interpolation LGL(N) -> solution nodes */
+  xr *xL, *xgL, *DgL, *Mg2sL;  /* extended-precision copies for the set-up */
   /* geometry */
   double *XL;  /* [E][n3][3]  positions on LGL(N)                        */
   double *Xs;  /* [E][n3][3]  positions at the solution nodes             */
@@ -73,63 +76,64 @@ typedef struct orc {
 /* Gauss-Lobatto nodes, Lagrange basis.                                     */
 /* ------------------------------------------------------------------------ */
 
+
 /* Legendre P_m(x) and P_m'(x) by the three-term recurrence. */
-static void legendre(int m, double x, double *P, double *dP) {
-  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
-  if (m == 0) { *P = 1.0; *dP = 0.0; return; }
+static void legendre(int m, xr x, xr *P, xr *dP) {
+  xr p0 = 1.0L, p1 = x, d0 = 0.0L, d1 = 1.0L;
+  if (m == 0) { *P = 1.0L; *dP = 0.0L; return; }
   for (int k = 2; k <= m; ++k) {
-    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-    double d2 = d0 + (2.0 * k - 1.0) * p1;
+    xr p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+    xr d2 = d0 + (2.0L * k - 1.0L) * p1;
     p0 = p1; p1 = p2; d0 = d1; d1 = d2;
   }
   *P = p1; *dP = d1;
 }
 
 /* Legendre-Gauss nodes: roots of P_{N+1}; weights 2/((1-x^2) P'_{N+1}^2). */
-static void gauss_nodes(int N, double *x, double *w) {
+static void gauss_nodes(int N, xr *x, xr *w) {
   int n = N + 1;
   for (int k = 0; k < n; ++k) {
-    double xk = -cos((2.0 * k + 1.0) * M_PI / (2.0 * N + 2.0));
+    xr xk = -cosl((2.0L * k + 1.0L) * XPI / (2.0L * N + 2.0L));
     for (int it = 0; it < 100; ++it) {
-      double P, dP;
+      xr P, dP;
       legendre(n, xk, &P, &dP);
-      double dx = P / dP;
+      xr dx = P / dP;
       xk -= dx;
-      if (fabs(dx) < 1e-16) break;
+      if (fabsl(dx) < 1e-19L) break;
     }
-    double P, dP;
+    xr P, dP;
     legendre(n, xk, &P, &dP);
     x[k] = xk;
-    w[k] = 2.0 / ((1.0 - xk * xk) * dP * dP);
+    w[k] = 2.0L / ((1.0L - xk * xk) * dP * dP);
   }
 }
 
 /* Legendre-Gauss-Lobatto nodes: -1, roots of P_N', +1;
  * weights 2/(N(N+1) P_N^2).  P_N'' from the Legendre equation. */
-static void lobatto_nodes(int N, double *x, double *w) {
-  x[0] = -1.0; x[N] = 1.0;
+static void lobatto_nodes(int N, xr *x, xr *w) {
+  x[0] = -1.0L; x[N] = 1.0L;
   for (int k = 1; k < N; ++k) {
-    double xk = -cos(M_PI * k / N);
+    xr xk = -cosl(XPI * k / N);
     for (int it = 0; it < 100; ++it) {
-      double P, dP;
+      xr P, dP;
       legendre(N, xk, &P, &dP);
-      double d2P = (2.0 * xk * dP - N * (N + 1.0) * P) / (1.0 - xk * xk);
-      double dx = dP / d2P;
+      xr d2P = (2.0L * xk * dP - N * (N + 1.0L) * P) / (1.0L - xk * xk);
+      xr dx = dP / d2P;
       xk -= dx;
-      if (fabs(dx) < 1e-16) break;
+      if (fabsl(dx) < 1e-19L) break;
     }
     x[k] = xk;
   }
   for (int k = 0; k <= N; ++k) {
-    double P, dP;
+    xr P, dP;
     legendre(N, x[k], &P, &dP);
-    w[k] = 2.0 / (N * (N + 1.0) * P * P);
+    w[k] = 2.0L / (N * (N + 1.0L) * P * P);
   }
 }
 
 /* Lagrange polynomial l_j(s) = prod_{i != j} (s - x_i)/(x_j - x_i). */
-static double lagrange(int n, const double *xn, int j, double s) {
-  double r = 1.0;
+static xr lagrange(int n, const xr *xn, int j, xr s) {
+  xr r = 1.0L;
   for (int i = 0; i < n; ++i)
     if (i != j) r *= (s - xn[i]) / (xn[j] - xn[i]);
   return r;
@@ -137,13 +141,13 @@ static double lagrange(int n, const double *xn, int j, double s) {
 
 /* D_ij = l_j'(x_i): for i != j from the derivative of the product formula
  * evaluated at a node, D_ii = -sum_{j != i} D_ij (exact for constants). */
-static void diff_matrix(int n, const double *xn, double *D) {
+static void diff_matrix(int n, const xr *xn, xr *D) {
   for (int i = 0; i < n; ++i) {
-    double s = 0.0;
+    xr s = 0.0L;
     for (int j = 0; j < n; ++j) {
       if (i == j) continue;
       /* l_j'(x_i) = prod_{k != j, k != i}(x_i - x_k) / prod_{k != j}(x_j - x_k) */
-      double num = 1.0, den = 1.0;
+      xr num = 1.0L, den = 1.0L;
       for (int k = 0; k < n; ++k) {
         if (k != j && k != i) num *= (xn[i] - xn[k]);
         if (k != j) den *= (xn[j] - xn[k]);
@@ -156,7 +160,7 @@ static void diff_matrix(int n, const double *xn, double *D) {
 }
 
 /* M[b][a] = l_a(to_b): interpolation from nodes `from` to points `to`. */
-static void interp_matrix(int n, const double *from, int m, const double *to, double *M) {
+static void interp_matrix(int n, const xr *from, int m, const xr *to, xr *M) {
   for (int b = 0; b < m; ++b)
     for (int a = 0; a < n; ++a) M[b * n + a] = lagrange(n, from, a, to[b]);
 }
@@ -212,6 +216,48 @@ static void deriv_dir(int n, const double *D, int d, const double *f, int fs, do
     for (int p = 0; p < n; ++p)
       for (int l = 0; l < n; ++l) {
         double s = 0.0;
+        for (int a = 0; a < n; ++a) s += D[l * n + a] * f[line_node(n, d, a, p, q) * fs];
+        out[line_node(n, d, l, p, q) * os] = s;
+      }
+}
+
+/* the same two helpers in extended precision, for the set-up */
+static void interp3x(int n, int m, const xr *M, const xr *in, xr *out, int c) {
+  xr *t1 = (xr *)calloc((size_t)m * n * n * c, sizeof(xr));
+  xr *t2 = (xr *)calloc((size_t)m * m * n * c, sizeof(xr));
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int a = 0; a < m; ++a)
+        for (int v = 0; v < c; ++v) {
+          xr s = 0.0L;
+          for (int i = 0; i < n; ++i) s += M[a * n + i] * in[(i + n * (j + n * k)) * c + v];
+          t1[(a + m * (j + n * k)) * c + v] = s;
+        }
+  for (int k = 0; k < n; ++k)
+    for (int b = 0; b < m; ++b)
+      for (int a = 0; a < m; ++a)
+        for (int v = 0; v < c; ++v) {
+          xr s = 0.0L;
+          for (int j = 0; j < n; ++j) s += M[b * n + j] * t1[(a + m * (j + n * k)) * c + v];
+          t2[(a + m * (b + m * k)) * c + v] = s;
+        }
+  for (int g = 0; g < m; ++g)
+    for (int b = 0; b < m; ++b)
+      for (int a = 0; a < m; ++a)
+        for (int v = 0; v < c; ++v) {
+          xr s = 0.0L;
+          for (int k = 0; k < n; ++k) s += M[g * n + k] * t2[(a + m * (b + m * k)) * c + v];
+          out[(a + m * (b + m * g)) * c + v] = s;
+        }
+  free(t1);
+  free(t2);
+}
+
+static void deriv_dirx(int n, const xr *D, int d, const xr *f, int fs, xr *out, int os) {
+  for (int q = 0; q < n; ++q)
+    for (int p = 0; p < n; ++p)
+      for (int l = 0; l < n; ++l) {
+        xr s = 0.0L;
         for (int a = 0; a < n; ++a) s += D[l * n + a] * f[line_node(n, d, a, p, q) * fs];
         out[line_node(n, d, l, p, q) * os] = s;
       }
@@ -365,54 +411,61 @@ static void build_basis(orc *o) {
   o->D = ALLOC(double, n * n); o->Dhat = ALLOC(double, n * n);
   o->lm = ALLOC(double, n); o->lp = ALLOC(double, n);
   o->lhm = ALLOC(double, n); o->lhp = ALLOC(double, n);
-  o->xg = ALLOC(double, n); o->wg = ALLOC(double, n); o->Dg = ALLOC(double, n * n);
-  o->Mg2s = ALLOC(double, n * n);
-  if (o->node_type == 0) gauss_nodes(o->N, o->x, o->w);
-  else lobatto_nodes(o->N, o->x, o->w);
-  lobatto_nodes(o->N, o->xg, o->wg);
-  diff_matrix(n, o->x, o->D);
-  diff_matrix(n, o->xg, o->Dg);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) o->Dhat[i * n + j] = -(o->w[j] / o->w[i]) * o->D[j * n + i];
+  o->xL = ALLOC(xr, n); o->xgL = ALLOC(xr, n); o->DgL = ALLOC(xr, n * n); o->Mg2sL = ALLOC(xr, n * n);
+  xr *wL = ALLOC(xr, n), *wgL = ALLOC(xr, n), *DL = ALLOC(xr, n * n);
+  if (o->node_type == 0) gauss_nodes(o->N, o->xL, wL);
+  else lobatto_nodes(o->N, o->xL, wL);
+  lobatto_nodes(o->N, o->xgL, wgL);
+  diff_matrix(n, o->xL, DL);
+  diff_matrix(n, o->xgL, o->DgL);
   for (int i = 0; i < n; ++i) {
-    o->lm[i] = lagrange(n, o->x, i, -1.0);
-    o->lp[i] = lagrange(n, o->x, i, 1.0);
-    o->lhm[i] = o->lm[i] / o->w[i];
-    o->lhp[i] = o->lp[i] / o->w[i];
+    o->x[i] = (double)o->xL[i];
+    o->w[i] = (double)wL[i];
   }
-  interp_matrix(n, o->xg, n, o->x, o->Mg2s);
+  for (int i = 0; i < n * n; ++i) o->D[i] = (double)DL[i];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) o->Dhat[i * n + j] = (double)(-(wL[j] / wL[i]) * DL[j * n + i]);
+  for (int i = 0; i < n; ++i) {
+    xr lm = lagrange(n, o->xL, i, -1.0L), lp = lagrange(n, o->xL, i, 1.0L);
+    o->lm[i] = (double)lm;
+    o->lp[i] = (double)lp;
+    o->lhm[i] = (double)(lm / wL[i]);
+    o->lhp[i] = (double)(lp / wL[i]);
+  }
+  interp_matrix(n, o->xgL, n, o->xL, o->Mg2sL);
   /* FV subcell interfaces: xi_{-1/2} = -1, xi_{m+1/2} = -1 + sum_{k<=m} w_k */
   o->xhalf = ALLOC(double, n + 1);
   o->xhalf[0] = -1.0;
   for (int m = 0; m < n; ++m) o->xhalf[m + 1] = o->xhalf[m] + o->w[m];
   /* orthonormal Legendre Vandermonde V_ia = sqrt((2a+1)/2) P_a(x_i), inverted by
    * Gauss-Jordan elimination with partial pivoting */
-  double *V = ALLOC(double, n * n), *I = ALLOC(double, n * n);
+  xr *V = ALLOC(xr, n * n), *I = ALLOC(xr, n * n);
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < n; ++a) {
-      double P, dP;
-      legendre(a, o->x[i], &P, &dP);
-      V[i * n + a] = sqrt((2.0 * a + 1.0) / 2.0) * P;
+      xr P, dP;
+      legendre(a, o->xL[i], &P, &dP);
+      V[i * n + a] = sqrtl((2.0L * a + 1.0L) / 2.0L) * P;
       I[i * n + a] = (i == a);
     }
   for (int c = 0; c < n; ++c) {
     int piv = c;
     for (int r = c + 1; r < n; ++r)
-      if (fabs(V[r * n + c]) > fabs(V[piv * n + c])) piv = r;
+      if (fabsl(V[r * n + c]) > fabsl(V[piv * n + c])) piv = r;
     for (int k = 0; k < n; ++k) {
-      double t = V[c * n + k]; V[c * n + k] = V[piv * n + k]; V[piv * n + k] = t;
+      xr t = V[c * n + k]; V[c * n + k] = V[piv * n + k]; V[piv * n + k] = t;
       t = I[c * n + k]; I[c * n + k] = I[piv * n + k]; I[piv * n + k] = t;
     }
-    double d = V[c * n + c];
+    xr d = V[c * n + c];
     for (int k = 0; k < n; ++k) { V[c * n + k] /= d; I[c * n + k] /= d; }
     for (int r = 0; r < n; ++r) {
       if (r == c) continue;
-      double f = V[r * n + c];
+      xr f = V[r * n + c];
       for (int k = 0; k < n; ++k) { V[r * n + k] -= f * V[c * n + k]; I[r * n + k] -= f * I[c * n + k]; }
     }
   }
-  o->Vinv = I;
-  free(V);
+  o->Vinv = ALLOC(double, n * n);
+  for (int i = 0; i < n * n; ++i) o->Vinv[i] = (double)I[i];
+  free(V); free(I); free(wL); free(wgL); free(DL);
 }
 
 /* Curl form of Sec. 2.2: Ja^i_n = -e_i . curl_xi (x_l grad_xi x_m), (n,m,l)
@@ -426,28 +479,29 @@ static void build_metrics(orc *o, const double *x_geo) {
   o->Ja = ALLOC(double, E * n3 * 9);
   o->J = ALLOC(double, E * n3);
   o->nS = ALLOC(double, E * 6 * o->n2 * 3);
-  double *xgeo_nodes = ALLOC(double, ng), *wgeo = ALLOC(double, ng);
+  xr *xgeo_nodes = ALLOC(xr, ng), *wgeo = ALLOC(xr, ng);
   lobatto_nodes(o->ngeo, xgeo_nodes, wgeo);
-  double *Mgeo = ALLOC(double, n * ng);
-  interp_matrix(ng, xgeo_nodes, n, o->xg, Mgeo);
+  xr *Mgeo = ALLOC(xr, n * ng);
+  interp_matrix(ng, xgeo_nodes, n, o->xgL, Mgeo);
 #pragma omp parallel for schedule(static)
   for (long e = 0; e < E; ++e) {
-    double *in = ALLOC(double, ng3 * 3);
+    xr *in = ALLOC(xr, ng3 * 3);
     for (int a = 0; a < ng3; ++a)
       for (int c = 0; c < 3; ++c) in[a * 3 + c] = x_geo[(e * 3 + c) * ng3 + a];
-    double *XL = o->XL + e * n3 * 3;
-    interp3(ng, n, Mgeo, in, XL, 3);
+    xr *XL = ALLOC(xr, n3 * 3);
+    interp3x(ng, n, Mgeo, in, XL, 3);
     free(in);
+    for (int a = 0; a < n3 * 3; ++a) o->XL[e * n3 * 3 + a] = (double)XL[a];
     /* dX[j][m] = d x_m / d xi_j on LGL(N) */
-    double *dX = ALLOC(double, n3 * 9);
+    xr *dX = ALLOC(xr, n3 * 9);
     for (int j = 0; j < 3; ++j)
-      for (int m = 0; m < 3; ++m) deriv_dir(n, o->Dg, j, XL + m, 3, dX + j * 3 + m, 9);
-    double *JaL = ALLOC(double, n3 * 9);
-    double *Vv = ALLOC(double, n3 * 3), *dV = ALLOC(double, n3);
+      for (int m = 0; m < 3; ++m) deriv_dirx(n, o->DgL, j, XL + m, 3, dX + j * 3 + m, 9);
+    xr *JaL = ALLOC(xr, n3 * 9);
+    xr *Vv = ALLOC(xr, n3 * 3), *dV = ALLOC(xr, n3);
     /* The curl form is unchanged by a constant shift of x (the discrete curl
      * of a discrete gradient vanishes, D_b D_c = D_c D_b); positions are taken
      * relative to the element's first geometry node to avoid cancellation. */
-    double x0[3] = {XL[0], XL[1], XL[2]};
+    xr x0[3] = {XL[0], XL[1], XL[2]};
     for (int nn = 0; nn < 3; ++nn) {
       int m = (nn + 1) % 3, l = (nn + 2) % 3;
       /* V_j = x_l d_j x_m, pointwise on the LGL grid */
@@ -456,52 +510,65 @@ static void build_metrics(orc *o, const double *x_geo) {
       /* (curl V)_0 = d1 V2 - d2 V1, (curl V)_1 = d2 V0 - d0 V2, (curl V)_2 = d0 V1 - d1 V0 */
       for (int i = 0; i < 3; ++i) {
         int b = (i + 1) % 3, c = (i + 2) % 3;
-        for (int a = 0; a < n3; ++a) JaL[a * 9 + i * 3 + nn] = 0.0;
-        deriv_dir(n, o->Dg, b, Vv + c, 3, dV, 1);
+        for (int a = 0; a < n3; ++a) JaL[a * 9 + i * 3 + nn] = 0.0L;
+        deriv_dirx(n, o->DgL, b, Vv + c, 3, dV, 1);
         for (int a = 0; a < n3; ++a) JaL[a * 9 + i * 3 + nn] -= dV[a];
-        deriv_dir(n, o->Dg, c, Vv + b, 3, dV, 1);
+        deriv_dirx(n, o->DgL, c, Vv + b, 3, dV, 1);
         for (int a = 0; a < n3; ++a) JaL[a * 9 + i * 3 + nn] += dV[a];
       }
     }
     free(Vv); free(dV);
     /* to the solution nodes */
-    interp3(n, n, o->Mg2s, JaL, o->Ja + e * n3 * 9, 9);
-    interp3(n, n, o->Mg2s, XL, o->Xs + e * n3 * 3, 3);
-    double *dXs = ALLOC(double, n3 * 9);
-    interp3(n, n, o->Mg2s, dX, dXs, 9);
+    xr *tmp = ALLOC(xr, n3 * 9);
+    interp3x(n, n, o->Mg2sL, JaL, tmp, 9);
+    for (int a = 0; a < n3 * 9; ++a) o->Ja[e * n3 * 9 + a] = (double)tmp[a];
+    interp3x(n, n, o->Mg2sL, XL, tmp, 3);
+    for (int a = 0; a < n3 * 3; ++a) o->Xs[e * n3 * 3 + a] = (double)tmp[a];
+    interp3x(n, n, o->Mg2sL, dX, tmp, 9);
     for (int a = 0; a < n3; ++a) {
-      const double *A = dXs + a * 9; /* A[j*3+m] = d x_m / d xi_j */
-      o->J[e * n3 + a] = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
-                         A[2] * (A[3] * A[7] - A[4] * A[6]);
+      const xr *A = tmp + a * 9; /* A[j*3+m] = d x_m / d xi_j */
+      o->J[e * n3 + a] = (double)(A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                                  A[2] * (A[3] * A[7] - A[4] * A[6]));
     }
-    free(dXs);
+    free(tmp);
     /* face metrics: Ja^d on the LGL face slice, 2-D interpolated to the
      * solution face nodes; outward n*shat = +-Ja^d */
     for (int f = 0; f < 6; ++f) {
       int d = f / 2, side = f % 2;
       int l = side ? n - 1 : 0;
-      double sgn = side ? 1.0 : -1.0;
+      xr sgn = side ? 1.0L : -1.0L;
       for (int q = 0; q < n; ++q)
         for (int p = 0; p < n; ++p) {
-          double a[3] = {0, 0, 0};
+          xr a[3] = {0, 0, 0};
           for (int qq = 0; qq < n; ++qq)
             for (int pp = 0; pp < n; ++pp) {
-              double wgt = o->Mg2s[p * n + pp] * o->Mg2s[q * n + qq];
+              xr wgt = o->Mg2sL[p * n + pp] * o->Mg2sL[q * n + qq];
               int a_node = line_node(n, d, l, pp, qq);
               for (int c = 0; c < 3; ++c) a[c] += wgt * JaL[a_node * 9 + d * 3 + c];
             }
           double *ns = o->nS + ((e * 6 + f) * o->n2 + p + n * q) * 3;
-          for (int c = 0; c < 3; ++c) ns[c] = sgn * a[c];
+          for (int c = 0; c < 3; ++c) ns[c] = (double)(sgn * a[c]);
         }
     }
-    free(JaL); free(dX);
+    free(JaL); free(dX); free(XL);
   }
   free(xgeo_nodes); free(wgeo); free(Mgeo);
 }
 
 /* Unstructured connectivity (Sec. 2.2, last paragraph; App. A ProlongToFace):
  * the node correspondence on each face is recovered from coincident physical
- * positions of the LGL(N) face nodes, modulo the periodic box. */
+ * positions of the LGL(N) face nodes, modulo the periodic box.  Two faces are
+ * related by a relative rotation or reflection of the face frame, i.e. one of
+ * the eight symmetries of the square grid.  A face that touches its own
+ * periodic image (one element across the box) has edge nodes that coincide
+ * with several neighbour nodes modulo the period, so the correspondence is
+ * the unique symmetry under which every node lands on a coincident node. */
+static void square_map(int code, int n, int p, int q, int *pp, int *qq) {
+  int a = (code & 1) ? q : p, b = (code & 1) ? p : q;
+  *pp = (code & 2) ? n - 1 - a : a;
+  *qq = (code & 4) ? n - 1 - b : b;
+}
+
 static int match_faces(orc *o, const long *nbr_elem, const int8_t *nbr_face) {
   int n = o->n, n2 = o->n2;
   long E = o->E;
@@ -512,6 +579,7 @@ static int match_faces(orc *o, const long *nbr_elem, const int8_t *nbr_face) {
   long bad_e = -1; int bad_f = -1;
 #pragma omp parallel for schedule(static)
   for (long e = 0; e < E; ++e) {
+    char *coin = (char *)xalloc((size_t)n2 * n2);
     for (int f = 0; f < 6; ++f) {
       long e2 = nbr_elem[e * 6 + f];
       int f2 = nbr_face[e * 6 + f];
@@ -531,31 +599,44 @@ static int match_faces(orc *o, const long *nbr_elem, const int8_t *nbr_face) {
       double hs = sqrt((c1[0] - c0[0]) * (c1[0] - c0[0]) + (c1[1] - c0[1]) * (c1[1] - c0[1]) +
                        (c1[2] - c0[2]) * (c1[2] - c0[2]));
       double tol = 1e-8 * hs;
-      for (int q = 0; q < n; ++q)
-        for (int p = 0; p < n; ++p) {
-          const double *xa = X1 + line_node(n, d, l, p, q) * 3;
-          int found = -1;
-          for (int qq = 0; qq < n && found < 0; ++qq)
-            for (int pp = 0; pp < n; ++pp) {
-              const double *xb = X2 + line_node(n, d2, l2, pp, qq) * 3;
-              double dist2 = 0.0;
-              for (int c = 0; c < 3; ++c) {
-                double dd = xa[c] - xb[c];
-                if (o->period[c] > 0.0) dd -= o->period[c] * nearbyint(dd / o->period[c]);
-                dist2 += dd * dd;
-              }
-              if (sqrt(dist2) <= tol) { found = pp + n * qq; break; }
-            }
-          if (found < 0) {
-#pragma omp critical
-            { bad = 1; bad_e = e; bad_f = f; }
+      /* coin[a][b]: own node a coincides with neighbour node b (mod period) */
+      for (int a = 0; a < n2; ++a)
+        for (int b = 0; b < n2; ++b) {
+          const double *xa = X1 + line_node(n, d, l, a % n, a / n) * 3;
+          const double *xb = X2 + line_node(n, d2, l2, b % n, b / n) * 3;
+          double dist2 = 0.0;
+          for (int c = 0; c < 3; ++c) {
+            double dd = xa[c] - xb[c];
+            if (o->period[c] > 0.0) dd -= o->period[c] * nearbyint(dd / o->period[c]);
+            dist2 += dd * dd;
           }
-          o->fmap[(e * 6 + f) * n2 + p + n * q] = found;
+          coin[a * n2 + b] = sqrt(dist2) <= tol;
         }
+      int found = -1, count = 0;
+      for (int code = 0; code < 8; ++code) {
+        int ok = 1;
+        for (int a = 0; a < n2 && ok; ++a) {
+          int pp, qq;
+          square_map(code, n, a % n, a / n, &pp, &qq);
+          ok = coin[a * n2 + pp + n * qq];
+        }
+        if (ok) { found = code; ++count; }
+      }
+      if (count != 1) {
+#pragma omp critical
+        { bad = 1; bad_e = e; bad_f = f; }
+        continue;
+      }
+      for (int a = 0; a < n2; ++a) {
+        int pp, qq;
+        square_map(found, n, a % n, a / n, &pp, &qq);
+        o->fmap[(e * 6 + f) * n2 + a] = pp + n * qq;
+      }
     }
+    free(coin);
   }
   if (bad) {
-    snprintf(o->err, sizeof o->err, "faces do not coincide: element %ld face %d", bad_e, bad_f);
+    snprintf(o->err, sizeof o->err, "faces do not coincide (or not uniquely): element %ld face %d", bad_e, bad_f);
     return -2;
   }
   return 0;
@@ -603,8 +684,8 @@ orc *orc_create(int N, int node_type, int ngeo, long E, const double *x_geo, con
 
 void orc_destroy(orc *o) {
   if (!o) return;
-  void *ptrs[] = {o->x, o->w, o->D, o->Dhat, o->lm, o->lp, o->lhm, o->lhp, o->xg, o->wg, o->Dg,
-                  o->Mg2s, o->XL, o->Xs, o->Ja, o->J, o->nS, o->nbr, o->nbrf, o->fmap, o->alpha,
+  void *ptrs[] = {o->x, o->w, o->D, o->Dhat, o->lm, o->lp, o->lhm, o->lhp, o->xL, o->xgL, o->DgL,
+                  o->Mg2sL, o->XL, o->Xs, o->Ja, o->J, o->nS, o->nbr, o->nbrf, o->fmap, o->alpha,
                   o->Vinv, o->xhalf, o->Ui, o->prim, o->Uf, o->primf, o->G, o->Gf, o->V,
                   o->faceF, o->liftF, o->Vadv, o->Vvis, o->Vfv};
   for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
@@ -874,10 +955,20 @@ int orc_rhs(orc *o, const double *Usoa, double t, double *Utsoa) {
       }
     }
 
-  /* blending factors (Sec. 2.3), one per element */
+  /* blending factors (Sec. 2.3), one per element: the indicator value of the
+   * element, raised to half the largest value among its face neighbours so
+   * that elements about to be reached by a shock are already blended */
   if (o->shock && !o->alpha_frozen) {
+    double *raw = ALLOC(double, E);
 #pragma omp parallel for schedule(static)
-    for (long e = 0; e < E; ++e) o->alpha[e] = indicator_alpha(o, e);
+    for (long e = 0; e < E; ++e) raw[e] = indicator_alpha(o, e);
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < E; ++e) {
+      double a = raw[e];
+      for (int f = 0; f < 6; ++f) a = fmax(a, 0.5 * raw[o->nbr[e * 6 + f]]);
+      o->alpha[e] = fmin(a, o->alpha_max);
+    }
+    free(raw);
   }
 
   /* VolInt: contravariant fluxes F^i = Ja^i . (F_adv - F_v) at every node, then

@@ -38,6 +38,7 @@ struct View {
   const double *Xs; // [3][E][n3] node positions (manufactured source only)
   const real *basis; // operator block, see BasisOffsets
   real *alpha;      // [E] blending factors
+  real *alpha_raw;  // [E] indicator values before neighbour propagation
   const real *alpha_in; // [E] frozen blending factors or null
   real gamma, Rgas, mu, lambda; // perfect gas, constant viscosity and conductivity
   double Pr;        // Prandtl number (time-step estimate only)

@@ -123,9 +123,72 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *view
 }
 
 // ---------------------------------------------------------------------------
+// a-priori indicator (Sec. 2.3): modal energy of eps = rho p.  m = (V^-1 (x)
+// V^-1 (x) V^-1) eps by three line transforms through LDS rows r0..r2, then a
+// fixed-order tree reduction of the energies in rows r3..r5 (no atomics, so
+// the value is reproducible).  Every thread of the block must call it.
+// Returns the clipped logistic value on thread a == 0 of each element.
+// ---------------------------------------------------------------------------
+template <int N, typename real>
+__device__ __forceinline__ real indicator_raw(const View<real> &v, const real *Vinv, real *r0, real *r1, real *r2,
+                                              real *r3, real *r4, real *r5, bool active, int a, real eps) {
+  constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+  const int i = a % n, j = (a / n) % n, k = a / n2;
+  if (active) r0[a] = eps;
+  __syncthreads();
+  if (active) {
+    real t = real(0);
+#pragma unroll
+    for (int r = 0; r < n; ++r) t += Vinv[i * n + r] * r0[vnode(n, r, j, k)];
+    r1[a] = t;
+  }
+  __syncthreads();
+  if (active) {
+    real t = real(0);
+#pragma unroll
+    for (int r = 0; r < n; ++r) t += Vinv[j * n + r] * r1[vnode(n, i, r, k)];
+    r2[a] = t;
+  }
+  __syncthreads();
+  if (active) {
+    real m = real(0);
+#pragma unroll
+    for (int r = 0; r < n; ++r) m += Vinv[k * n + r] * r2[vnode(n, i, j, r)];
+    const real m2 = m * m;
+    r3[a] = m2;
+    r4[a] = (i < N && j < N && k < N) ? m2 : real(0);
+    r5[a] = (i < N - 1 && j < N - 1 && k < N - 1) ? m2 : real(0);
+  }
+  __syncthreads();
+  constexpr int P2 = n3 <= 8 ? 8 : (n3 <= 16 ? 16 : (n3 <= 32 ? 32 : (n3 <= 64 ? 64 : (n3 <= 128 ? 128 : (n3 <= 256 ? 256 : (n3 <= 512 ? 512 : 1024))))));
+#pragma unroll
+  for (int st = P2 / 2; st > 0; st >>= 1) {
+    if (active && a < st && a + st < n3) {
+      r3[a] += r3[a + st];
+      r4[a] += r4[a + st];
+      r5[a] += r5[a + st];
+    }
+    __syncthreads();
+  }
+  real alpha = real(0);
+  if (active && a == 0) {
+    const real tot = r3[0], c1 = r4[0], c2 = r5[0];
+    const real E1 = tot > real(0) ? (tot - c1) / tot : real(0);
+    const real E2 = c1 > real(0) ? (c1 - c2) / c1 : real(0);
+    const real Ev = fmax(E1, E2);
+    const real T = v.ind_T;
+    alpha = real(1) / (real(1) + exp(-(v.ind_s / T) * (Ev - T)));
+    if (alpha < v.alpha_min) alpha = real(0);
+    else if (alpha > real(1) - v.alpha_min) alpha = real(1);
+    alpha = fmin(alpha, v.alpha_max);
+  }
+  return alpha;
+}
+
+// ---------------------------------------------------------------------------
 // BR1 lifting: g = (1/J) [ sum_i D-hat (Ja^i_d v) + sum_faces v* (n shat)_d l-hat ]
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH>
+template <int N, typename real, bool BATCH, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads) k_lift(const View<real> *views, const int *blk_start, int nreq,
                                                         View<real> single) {
   using S = Sz<N>;
@@ -145,11 +208,26 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_lift(const View<real> *views
   const real gam = v.gamma, Rg = v.Rgas;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
+  real P[6];
   if (active) {
-    real U[5], P[6];
+    real U[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
     cons2prim(U, gam, Rg, P);
+  }
+  if constexpr (SHOCK) {
+    // indicator value of this element (neighbour propagation follows in k_rhs)
+    __shared__ real sVinv[n * n];
+    BasisOffsets o(n);
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) sVinv[t] = v.basis[o.Vinv + t];
+    __syncthreads();
+    const real al = indicator_raw<N, real>(v, sVinv, sV[le][0], sV[le][1], sV[le][2], sJ[le][0], sJ[le][1], sJ[le][2],
+                                           active, a, active ? P[0] * P[4] : real(0));
+    if (active && a == 0) v.alpha_raw[e] = al;
+    __syncthreads();
+  }
+  if (!v.viscous) return;  // uniform over the grid: the indicator was all that was asked
+  if (active) {
     sV[le][0][a] = P[1];
     sV[le][1][a] = P[2];
     sV[le][2][a] = P[3];
@@ -250,19 +328,55 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_lift(const View<real> *views
 
 // ---------------------------------------------------------------------------
 // Time derivative and stage update.  mode 0: du = A du + dt R, U += B du and
-// the next stage's traces; mode 1: write R only.
+// the next stage's traces; mode 1: write R only.  SHOCK adds the a-priori
+// indicator and the convex DG/FV-subcell blend of Sec. 2.3.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH>
+template <typename real>
+__device__ __forceinline__ real minmod2(real a, real b) {
+  if (a * b <= real(0)) return real(0);
+  return (a > real(0) ? real(1) : real(-1)) * fmin(fabs(a), fabs(b));
+}
+
+template <typename real>
+__device__ __forceinline__ void prim2cons(const real *q, real gamma, real *U) {
+  U[0] = q[0];
+  U[1] = q[0] * q[1];
+  U[2] = q[0] * q[2];
+  U[3] = q[0] * q[3];
+  U[4] = q[4] / (gamma - real(1)) + real(0.5) * q[0] * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+}
+
+template <int N, typename real, bool BATCH, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views, const int *blk_start, int nreq,
                                                        View<real> single, int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
+  // LDS rows of n3 values per element: 0-4 contravariant flux (advective part
+  // when blending), 5-9 viscous contravariant flux; the blend reuses 0-15 for
+  // the indicator and the subcell operator before the volume integral.
+  constexpr int ROWS = SHOCK ? 16 : 5;
   int lblk;
   const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
-  __shared__ real sF[epb][5][n3];
+  __shared__ real sB[epb][ROWS][n3];
   __shared__ real sS[epb][5][nf];
+  __shared__ real sFV[SHOCK ? (2 * n * n + 3 * n + 1) : 1];  // D, Vinv, w, x, xhalf
+  __shared__ real sAl[epb];
+  __shared__ int sAny;
   load_basis<N, real>(sb, v.basis);
+  if constexpr (SHOCK) {
+    BasisOffsets o(n);
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+      sFV[t] = v.basis[o.D + t];
+      sFV[n * n + t] = v.basis[o.Vinv + t];
+    }
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      sFV[2 * n * n + t] = v.basis[o.w + t];
+      sFV[2 * n * n + n + t] = v.basis[o.x + t];
+    }
+    for (int t = threadIdx.x; t < n + 1; t += blockDim.x) sFV[2 * n * n + 2 * n + t] = v.basis[o.xhalf + t];
+    if (threadIdx.x == 0) sAny = 0;
+  }
   const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
   const int64_t e = (int64_t)lblk * epb + le;
   const bool active = le < epb && e < v.E;
@@ -274,28 +388,34 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views,
   const int i = a % n, j = (a / n) % n, k = a / n2;
 
   real Ja[9];
-  real Fx[5], Fy[5], Fz[5];
+  real Fx[5], Fy[5], Fz[5];         // F_adv - F_visc (F_adv when SHOCK)
+  real Vx[5], Vy[5], Vz[5];         // F_visc (SHOCK only)
+  real P[6];
   if (active) {
-    real U[5], P[6];
+    real U[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
     cons2prim(U, gam, Rg, P);
     flux_adv<0>(U, P, Fx);
     flux_adv<1>(U, P, Fy);
     flux_adv<2>(U, P, Fz);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Vx[c] = Vy[c] = Vz[c] = real(0);
     if (visc) {
-      real g[12], Gv[5];
+      real g[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) g[c] = v.G[((int64_t)c * E + e) * n3 + a];
-      flux_visc<0>(P, g, mu, lam, Gv);
+      flux_visc<0>(P, g, mu, lam, Vx);
+      flux_visc<1>(P, g, mu, lam, Vy);
+      flux_visc<2>(P, g, mu, lam, Vz);
+      if constexpr (!SHOCK) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) Fx[c] -= Gv[c];
-      flux_visc<1>(P, g, mu, lam, Gv);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) Fy[c] -= Gv[c];
-      flux_visc<2>(P, g, mu, lam, Gv);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) Fz[c] -= Gv[c];
+        for (int c = 0; c < 5; ++c) {
+          Fx[c] -= Vx[c];
+          Fy[c] -= Vy[c];
+          Fz[c] -= Vz[c];
+        }
+      }
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) Ja[c] = v.Ja[((int64_t)c * E + e) * n3 + a];
@@ -358,31 +478,164 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views,
     }
   }
 
+  real al = real(0);
+  real Vfv[5] = {0, 0, 0, 0, 0};
+  if constexpr (SHOCK) {
+    const real *Dm = sFV;
+    const real *Vinv = sFV + n * n;
+    const real *wq = sFV + 2 * n * n;
+    const real *xq = sFV + 2 * n * n + n;
+    const real *xh = sFV + 2 * n * n + 2 * n;
+    __syncthreads();
+    if (active && a == 0) {
+      real a0;
+      if (v.alpha_in) {
+        a0 = v.alpha_in[e];
+      } else {
+        // the element's indicator value, raised to half of its face neighbours'
+        a0 = v.alpha_raw[e];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) a0 = fmax(a0, real(0.5) * v.alpha_raw[v.conn[e * 6 + f].x / 6]);
+        a0 = fmin(a0, v.alpha_max);
+      }
+      sAl[le] = a0;
+    }
+    __syncthreads();
+    if (active) {
+      al = sAl[le];
+      if (a == 0) v.alpha[e] = al;
+      if (al > real(0)) sAny = 1;  // benign: every writer stores 1
+    }
+    __syncthreads();
+    if (sAny) {
+      // FV subcell operator (Sec. 2.3): rows 0-4 primitives, 5-7 Ja^d,
+      // 8-10 w_l d(Ja^d)/dxi, 11-15 interface fluxes
+      if (active) {
+        sB[le][0][a] = P[0];
+        sB[le][1][a] = P[1];
+        sB[le][2][a] = P[2];
+        sB[le][3][a] = P[3];
+        sB[le][4][a] = P[4];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int l = d == 0 ? i : (d == 1 ? j : k);
+        const int pp = d == 0 ? j : i, qq = d == 2 ? j : k;
+        if (active) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sB[le][5 + c][a] = Ja[3 * d + c];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            real s = real(0);
+#pragma unroll
+            for (int m = 0; m < n; ++m) s += Dm[l * n + m] * sB[le][5 + c][lnode<n>(d, m, pp, qq)];
+            sB[le][8 + c][a] = wq[l] * s;
+          }
+        }
+        __syncthreads();
+        if (active && l < N) {
+          real Jh[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            real acc = sB[le][5 + c][lnode<n>(d, 0, pp, qq)];
+            for (int m = 0; m <= l; ++m) acc += sB[le][8 + c][lnode<n>(d, m, pp, qq)];
+            Jh[c] = acc;
+          }
+          const real sh = sqrt(Jh[0] * Jh[0] + Jh[1] * Jh[1] + Jh[2] * Jh[2]);
+          const real nv[3] = {Jh[0] / sh, Jh[1] / sh, Jh[2] / sh};
+          real qL[5], qR[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            const real q0 = sB[le][c][lnode<n>(d, l, pp, qq)];
+            const real q1 = sB[le][c][lnode<n>(d, l + 1, pp, qq)];
+            real s0 = real(0), s1 = real(0);
+            if (l >= 1) {
+              const real qm = sB[le][c][lnode<n>(d, l - 1, pp, qq)];
+              s0 = minmod2((q0 - qm) / (xq[l] - xq[l - 1]), (q1 - q0) / (xq[l + 1] - xq[l]));
+            }
+            if (l + 1 <= N - 1) {
+              const real q2 = sB[le][c][lnode<n>(d, l + 2, pp, qq)];
+              s1 = minmod2((q1 - q0) / (xq[l + 1] - xq[l]), (q2 - q1) / (xq[l + 2] - xq[l + 1]));
+            }
+            qL[c] = q0 + s0 * (xh[l + 1] - xq[l]);
+            qR[c] = q1 - s1 * (xq[l + 1] - xh[l + 1]);
+          }
+          real UL[5], UR[5], PL[6], PR[6], F[5];
+          prim2cons(qL, gam, UL);
+          prim2cons(qR, gam, UR);
+          cons2prim(UL, gam, Rg, PL);
+          cons2prim(UR, gam, Rg, PR);
+          riemann_llf(UL, PL, UR, PR, nv, gam, F);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sB[le][11 + c][a] = F[c] * sh;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            real r = real(0);
+            if (l < N) r += sB[le][11 + c][a];
+            if (l > 0) r -= sB[le][11 + c][lnode<n>(d, l - 1, pp, qq)];
+            Vfv[c] += r / wq[l];
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
   // VolInt: one computational direction at a time through LDS
   real V[5] = {0, 0, 0, 0, 0};
+  real Vv[5] = {0, 0, 0, 0, 0};
+  const bool split = SHOCK && al > real(0);
 #pragma unroll
   for (int ci = 0; ci < 3; ++ci) {
     if (active) {
+      if constexpr (SHOCK) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c)
-        sF[le][c][a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
+        for (int c = 0; c < 5; ++c) {
+          if (split) {
+            sB[le][c][a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
+            sB[le][5 + c][a] = Ja[3 * ci + 0] * Vx[c] + Ja[3 * ci + 1] * Vy[c] + Ja[3 * ci + 2] * Vz[c];
+          } else {
+            sB[le][c][a] = Ja[3 * ci + 0] * (Fx[c] - Vx[c]) + Ja[3 * ci + 1] * (Fy[c] - Vy[c]) +
+                           Ja[3 * ci + 2] * (Fz[c] - Vz[c]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+          sB[le][c][a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
+      }
     }
     __syncthreads();
     if (active) {
       const int idx = ci == 0 ? i : (ci == 1 ? j : k);
 #pragma unroll
-      for (int al = 0; al < n; ++al) {
-        const int src = ci == 0 ? vnode(n, al, j, k) : (ci == 1 ? vnode(n, i, al, k) : vnode(n, i, j, al));
-        const real dh = sb.Dh[idx * n + al];
+      for (int alp = 0; alp < n; ++alp) {
+        const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
+        const real dh = sb.Dh[idx * n + alp];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) V[c] += dh * sF[le][c][src];
+        for (int c = 0; c < 5; ++c) V[c] += dh * sB[le][c][src];
+        if (split) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) Vv[c] -= dh * sB[le][5 + c][src];
+        }
       }
     }
     __syncthreads();
   }
 
-  double Unew[5];
+  double Unew[5] = {0, 0, 0, 0, 0};
   if (active) {
+    if (split) {
+      // (1 - alpha) V_DG,adv + alpha V_FV + V_DG,visc
+#pragma unroll
+      for (int c = 0; c < 5; ++c) V[c] = (real(1) - al) * V[c] + al * Vfv[c] + Vv[c];
+    }
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -425,7 +678,7 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views,
     // ProlongToFace of the updated state for the next stage
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) sF[le][c][a] = (real)Unew[c];
+      for (int c = 0; c < 5; ++c) sB[le][c][a] = (real)Unew[c];
     }
     __syncthreads();
     if (active) {
@@ -437,7 +690,7 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views,
         for (int c = 0; c < 5; ++c) {
           real s = real(0);
 #pragma unroll
-          for (int l = 0; l < n; ++l) s += lv[l] * sF[le][c][lnode<n>(d, l, p, q)];
+          for (int l = 0; l < n; ++l) s += lv[l] * sB[le][c][lnode<n>(d, l, p, q)];
           trn[(int64_t)c * Ef + (e * 6) * n2 + fn] = s;
         }
       }
@@ -592,12 +845,26 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
       else k_trace<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       break;
     case K_LIFT:
-      if (batch) k_lift<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-      else k_lift<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+      if (v0.shock) {
+        if (batch) k_lift<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        else k_lift<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+      } else {
+        if (batch) k_lift<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        else k_lift<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+      }
       break;
     case K_RHS:
-      if (batch) k_rhs<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-      else k_rhs<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+      if (v0.shock) {
+        if constexpr (N >= 2) {
+          if (batch) k_rhs<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          else k_rhs<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        } else {
+          return hipErrorInvalidValue;
+        }
+      } else {
+        if (batch) k_rhs<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        else k_rhs<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+      }
       break;
     default: return hipErrorInvalidValue;
   }

@@ -1,20 +1,469 @@
-// server.cpp -- continuous-batching server (placeholder until implemented).
+// server.cpp -- continuous batching of many independent DGSEM solves on one GPU.
+//
+// Requests are queued with their parameters, mesh and initial state.  Each
+// call of the loop (dg_server_run) repeats: admit queued requests in arrival
+// order while the memory budget and the slot table allow (strict FIFO: the
+// head of the queue is never overtaken); run one RK stage for every active
+// request -- one launch per kernel for every group of requests sharing
+// (N, precision, shock capturing), each workgroup finding its request through
+// block prefix sums and a device array of per-request views; retire requests
+// whose last stage has run: copy the state out and release the memory once
+// the copy has completed.  A request's arithmetic does not depend on what
+// else is in the batch, so each result equals the same solve run alone.
+//
+// The paper overlaps one solve's kernels on prioritised streams (Sec. 3.2);
+// the serving loop instead fills the GPU with the stages of many solves.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <vector>
+
 #include "dg_internal.h"
 #include "solver_impl.h"
 
 using namespace dg;
 
+namespace {
+
+constexpr int kDescSlots = 16;  // ring of descriptor uploads in flight
+
+struct Request {
+  int64_t id = 0;
+  dg_params p{};
+  int64_t E = 0;
+  int n_geo = 1;
+  std::vector<double> x_geo;
+  std::vector<int64_t> nbr_elem;
+  std::vector<int8_t> nbr_face, nbr_orient;
+  std::vector<double> U0;
+  int32_t n_steps = 0;
+  double dt = 0.0;
+  double t_arrival = 0.0, t_admit = -1.0, t_done = -1.0;
+  int32_t state = DG_REQ_QUEUED;
+  // while active
+  size_t off = 0, bytes = 0;
+  Layout L{};
+  View<double> vd{};
+  View<float> vf{};
+  int step = 0, stage = 0, cur = 0;
+  double t = 0.0;
+  bool traces_valid = false;
+  std::unique_ptr<Staging> staging;
+  hipEvent_t ready = nullptr;  // set-up copies done
+  // retirement
+  std::vector<double> result;
+  double *pinned = nullptr;
+  int *flag_host = nullptr;
+  hipEvent_t done_ev = nullptr;
+  bool retiring = false;
+};
+
+// first-fit allocator over [0, budget) of the arena, 256-byte granules
+struct Arena {
+  size_t budget = 0;
+  std::map<size_t, size_t> free_;  // offset -> size
+  void init(size_t base, size_t size) {
+    free_.clear();
+    budget = size;
+    free_[base] = size;
+  }
+  bool alloc(size_t bytes, size_t &off) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        off = it->first;
+        size_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+}  // namespace
+
+struct dg_server {
+  char *arena = nullptr;
+  size_t arena_bytes = 0, budget = 0;
+  int max_active = 0;
+  hipStream_t st = nullptr, cst = nullptr;
+  Arena alloc;
+  // descriptor ring: device region at the arena head, pinned host mirrors
+  size_t desc_stride = 0;
+  char *desc_host[kDescSlots] = {};
+  hipEvent_t desc_ev[kDescSlots] = {};
+  int desc_next = 0;
+  int *flags_dev = nullptr;
+  std::map<int64_t, std::unique_ptr<Request>> reqs;
+  std::deque<int64_t> queue;
+  std::vector<int64_t> active;
+  int64_t next_id = 1;
+  std::chrono::steady_clock::time_point t0;
+  bool broken = false;
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+size_t view_bytes() { return std::max(sizeof(View<double>), sizeof(View<float>)); }
+
+dg_status server_fail(dg_server *sv, hipError_t e, const char *what) {
+  sv->broken = true;
+  return fail(DG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// admit the head of the queue while it fits
+dg_status admit(dg_server *sv) {
+  double now = sv->now();
+  while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active) {
+    Request &r = *sv->reqs[sv->queue.front()];
+    if (r.t_arrival > now) break;
+    size_t off;
+    if (!sv->alloc.alloc(r.L.total, off)) break;  // wait for memory to free up
+    sv->queue.pop_front();
+    r.off = off;
+    r.bytes = r.L.total;
+    void *base = sv->arena + off;
+    fill_view(r.vd, base, r.L, r.p, r.E);
+    fill_view(r.vf, base, r.L, r.p, r.E);
+    dg_mesh m{r.E, r.n_geo, 0, r.x_geo.data(), r.nbr_elem.data(), r.nbr_face.data(), r.nbr_orient.data()};
+    r.staging.reset(new Staging());
+    dg_status rc = setup_upload(r.p, m, base, r.L, sv->cst, *r.staging);
+    hipError_t e = hipSuccess;
+    if (rc == DG_OK) {
+      r.staging->d.push_back(std::move(r.U0));
+      const std::vector<double> &u = r.staging->d.back();
+      e = hipMemcpyAsync((char *)base + r.L.U, u.data(), u.size() * 8, hipMemcpyHostToDevice, sv->cst);
+      if (e == hipSuccess && r.dt <= 0.0) {
+        // time step from the initial state: CFL = DFL = -dt (needs the value on the host now)
+        double *scr = (double *)((char *)base + r.L.scratch);
+        e = r.p.precision ? launch_dt<float>(r.p.N, r.vf, scr, kRedBlocks, sv->cst)
+                          : launch_dt<double>(r.p.N, r.vd, scr, kRedBlocks, sv->cst);
+        std::vector<double> h(2 * kRedBlocks);
+        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), scr, h.size() * 8, hipMemcpyDeviceToHost, sv->cst);
+        if (e == hipSuccess) e = hipStreamSynchronize(sv->cst);
+        double da = 1e300, dv = 1e300;
+        for (int b = 0; b < kRedBlocks; ++b) {
+          da = std::min(da, h[2 * b]);
+          dv = std::min(dv, h[2 * b + 1]);
+        }
+        const double cfl = -r.dt;
+        r.dt = std::min(cfl * da, cfl * dv);
+        if (!(r.dt > 0.0 && r.dt < 1e299)) rc = DG_ENONFINITE;
+      }
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(r.ready, sv->cst);
+      if (e == hipSuccess) e = hipStreamWaitEvent(sv->st, r.ready, 0);
+      if (e != hipSuccess) return server_fail(sv, e, "admission upload");
+    }
+    if (rc != DG_OK) {  // the mesh was validated at submit; a failure here retires the request
+      sv->alloc.release(r.off, r.bytes);
+      r.state = DG_REQ_FAILED;
+      r.t_done = sv->now();
+      continue;
+    }
+    r.state = DG_REQ_RUNNING;
+    r.t_admit = sv->now();
+    r.t = 0.0;
+    r.step = r.stage = r.cur = 0;
+    r.traces_valid = false;
+    sv->active.push_back(r.id);
+    if (r.n_steps == 0) r.step = r.n_steps;
+  }
+  return DG_OK;
+}
+
+template <typename real>
+View<real> &view_of(Request &r);
+template <>
+View<double> &view_of<double>(Request &r) {
+  return r.vd;
+}
+template <>
+View<float> &view_of<float>(Request &r) {
+  return r.vf;
+}
+
+// one batched launch of kernel k over the group; descriptors go through the ring
+template <typename real>
+dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request *> &grp) {
+  if (grp.empty()) return DG_OK;
+  const int slot = sv->desc_next;
+  sv->desc_next = (sv->desc_next + 1) % kDescSlots;
+  hipError_t e = hipEventSynchronize(sv->desc_ev[slot]);  // the upload that last used this slot is done
+  if (e != hipSuccess) return server_fail(sv, e, "descriptor ring");
+  char *h = sv->desc_host[slot];
+  View<real> *views = (View<real> *)h;
+  int *blk = (int *)(h + sv->max_active * view_bytes());
+  int total = 0;
+  for (size_t r = 0; r < grp.size(); ++r) {
+    Request &q = *grp[r];
+    View<real> v = view_of<real>(q);
+    v.t = q.t + RK_C[q.stage] * q.dt;
+    v.dt = q.dt;
+    v.rkA = RK_A[q.stage];
+    v.rkB = RK_B[q.stage];
+    v.cur = q.cur;
+    v.R = nullptr;
+    views[r] = v;
+    blk[r] = total;
+    total += blocks_per_elements(N, q.E);
+  }
+  blk[grp.size()] = total;
+  char *d = sv->arena + slot * sv->desc_stride;
+  e = hipMemcpyAsync(d, h, sv->desc_stride, hipMemcpyHostToDevice, sv->st);
+  if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[slot], sv->st);
+  if (e == hipSuccess)
+    e = launch<real>(k, N, 0, (const View<real> *)d, (const int *)(d + sv->max_active * view_bytes()), (int)grp.size(),
+                     total, views[0], sv->st);
+  if (e != hipSuccess) return server_fail(sv, e, "batched launch");
+  return DG_OK;
+}
+
+// one RK stage for every active request
+dg_status tick(dg_server *sv) {
+  std::map<std::tuple<int, int, int>, std::vector<Request *>> groups;
+  for (int64_t id : sv->active) {
+    Request &r = *sv->reqs[id];
+    if (r.retiring || r.step >= r.n_steps) continue;
+    groups[{r.p.N, r.p.precision, r.p.shock_capturing}].push_back(&r);
+  }
+  for (auto &kv : groups) {
+    const int N = std::get<0>(kv.first);
+    const bool mixed = std::get<1>(kv.first) == 1;
+    std::vector<Request *> fresh, visc;
+    for (Request *r : kv.second) {
+      if (!r->traces_valid) fresh.push_back(r);
+      if (r->p.viscous || r->p.shock_capturing) visc.push_back(r);
+    }
+    dg_status rc;
+    rc = mixed ? launch_group<float>(sv, K_TRACE, N, fresh) : launch_group<double>(sv, K_TRACE, N, fresh);
+    if (rc) return rc;
+    rc = mixed ? launch_group<float>(sv, K_LIFT, N, visc) : launch_group<double>(sv, K_LIFT, N, visc);
+    if (rc) return rc;
+    rc = mixed ? launch_group<float>(sv, K_RHS, N, kv.second) : launch_group<double>(sv, K_RHS, N, kv.second);
+    if (rc) return rc;
+    for (Request *r : kv.second) {
+      r->traces_valid = true;
+      r->cur ^= 1;
+      if (++r->stage == 5) {
+        r->stage = 0;
+        ++r->step;
+        r->t = r->step * r->dt;
+      }
+    }
+  }
+  return DG_OK;
+}
+
+// start the copy-out of finished requests; release those whose copy is done
+dg_status retire(dg_server *sv) {
+  std::vector<int64_t> keep;
+  for (int64_t id : sv->active) {
+    Request &r = *sv->reqs[id];
+    if (!r.retiring && r.step >= r.n_steps) {
+      const size_t cnt = (size_t)5 * r.E * (r.p.N + 1) * (r.p.N + 1) * (r.p.N + 1);
+      hipError_t e = hipHostMalloc((void **)&r.pinned, cnt * 8, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipHostMalloc((void **)&r.flag_host, 256 * sizeof(int), hipHostMallocDefault);
+      if (e != hipSuccess) return server_fail(sv, e, "pinned staging");
+      const double *U = (const double *)(sv->arena + r.off + r.L.U);
+      int *flags = (int *)(sv->arena + r.off + r.L.scratch);
+      e = launch_finite(U, (int64_t)cnt, flags, sv->st);
+      if (e == hipSuccess) e = hipMemcpyAsync(r.pinned, U, cnt * 8, hipMemcpyDeviceToHost, sv->st);
+      if (e == hipSuccess) e = hipMemcpyAsync(r.flag_host, flags, 256 * sizeof(int), hipMemcpyDeviceToHost, sv->st);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(r.done_ev, sv->st);
+      if (e != hipSuccess) return server_fail(sv, e, "retirement copy");
+      r.retiring = true;
+    }
+    if (r.retiring) {
+      hipError_t q = hipEventQuery(r.done_ev);
+      if (q == hipErrorNotReady) {
+        keep.push_back(id);
+        continue;
+      }
+      if (q != hipSuccess) return server_fail(sv, q, "retirement event");
+      const size_t cnt = (size_t)5 * r.E * (r.p.N + 1) * (r.p.N + 1) * (r.p.N + 1);
+      r.result.assign(r.pinned, r.pinned + cnt);
+      bool bad = false;
+      for (int b = 0; b < 256; ++b) bad |= r.flag_host[b] != 0;
+      (void)hipHostFree(r.pinned);
+      (void)hipHostFree(r.flag_host);
+      r.pinned = nullptr;
+      r.flag_host = nullptr;
+      (void)hipEventDestroy(r.done_ev);
+      r.done_ev = nullptr;
+      if (r.ready) (void)hipEventDestroy(r.ready);
+      r.ready = nullptr;
+      r.staging.reset();
+      sv->alloc.release(r.off, r.bytes);
+      r.state = bad ? DG_REQ_FAILED : DG_REQ_DONE;
+      r.t_done = sv->now();
+      continue;
+    }
+    // set-up staging can go once the uploads have landed
+    if (r.staging && r.ready && hipEventQuery(r.ready) == hipSuccess) r.staging.reset();
+    keep.push_back(id);
+  }
+  sv->active.swap(keep);
+  return DG_OK;
+}
+
+}  // namespace
+
 extern "C" {
-dg_status dg_server_create(void *, size_t, size_t, int32_t, void *, void *, dg_server **out) {
-  if (out) *out = nullptr;
-  return fail(DG_EINVAL, "server not available in this build");
+
+dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget, int32_t max_active, void *hip_stream,
+                           void *hip_copy_stream, dg_server **out) {
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d_arena || (uintptr_t)d_arena % 256) return fail(DG_EINVAL, "arena must be non-NULL and 256-byte aligned");
+  if (max_active < 1 || max_active > 4096) return fail(DG_EINVAL, "max_active must be in 1..4096");
+  std::unique_ptr<dg_server> sv(new dg_server());
+  sv->arena = (char *)d_arena;
+  sv->arena_bytes = arena_bytes;
+  sv->max_active = max_active;
+  sv->st = (hipStream_t)hip_stream;
+  sv->cst = hip_copy_stream ? (hipStream_t)hip_copy_stream : sv->st;
+  sv->desc_stride = ((max_active * view_bytes() + (max_active + 1) * sizeof(int)) + 255) & ~size_t(255);
+  const size_t head = kDescSlots * sv->desc_stride;
+  if (arena_bytes <= head) return fail(DG_ENOMEM, "arena smaller than the descriptor ring");
+  sv->budget = std::min(hbm_budget, arena_bytes - head);
+  sv->alloc.init(head, sv->budget);
+  for (int s = 0; s < kDescSlots; ++s) {
+    hipError_t e = hipHostMalloc((void **)&sv->desc_host[s], sv->desc_stride, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->desc_ev[s], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[s], sv->st);
+    if (e != hipSuccess) return fail(DG_EDEVICE, std::string("server set-up: ") + hipGetErrorString(e));
+  }
+  sv->t0 = std::chrono::steady_clock::now();
+  *out = sv.release();
+  return DG_OK;
 }
-dg_status dg_server_submit(dg_server *, const dg_params *, const dg_mesh *, const double *, int32_t, double, double,
-                           int64_t *) {
-  return fail(DG_EINVAL, "server not available in this build");
+
+dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, const double *U0_host, int32_t n_steps,
+                           double dt, double t_arrival, int64_t *req_id) {
+  if (!sv) return fail(DG_EINVAL, "server is NULL");
+  if (sv->broken) return fail(DG_ESTATE, "server unusable after a device error");
+  dg_status rc = check_params(p);
+  if (rc) return rc;
+  if (!m || !m->x_geo || !m->nbr_elem || !m->nbr_face || !m->nbr_orient || !U0_host || !req_id)
+    return fail(DG_EINVAL, "missing mesh, state or id pointer");
+  if (m->n_elems < 1 || m->n_elems * 6 >= INT32_MAX || m->n_geo < 1 || m->n_geo > p->N)
+    return fail(DG_EINVAL, "bad mesh sizes");
+  if (n_steps < 0 || !std::isfinite(dt) || dt == 0.0) return fail(DG_EINVAL, "need n_steps >= 0 and dt != 0");
+  std::unique_ptr<Request> r(new Request());
+  r->id = sv->next_id++;
+  r->p = *p;
+  r->E = m->n_elems;
+  r->n_geo = m->n_geo;
+  r->L = make_layout(*p, r->E);
+  if (r->L.total > sv->budget) return fail(DG_EBUSY, "request can never fit the memory budget");
+  const int ng = m->n_geo + 1, n = p->N + 1;
+  r->x_geo.assign(m->x_geo, m->x_geo + (size_t)r->E * 3 * ng * ng * ng);
+  r->nbr_elem.assign(m->nbr_elem, m->nbr_elem + r->E * 6);
+  r->nbr_face.assign(m->nbr_face, m->nbr_face + r->E * 6);
+  r->nbr_orient.assign(m->nbr_orient, m->nbr_orient + r->E * 6);
+  r->U0.assign(U0_host, U0_host + (size_t)5 * r->E * n * n * n);
+  r->n_steps = n_steps;
+  r->dt = dt;
+  r->t_arrival = t_arrival;
+  *req_id = r->id;
+  sv->queue.push_back(r->id);
+  sv->reqs[r->id] = std::move(r);
+  return DG_OK;
 }
-dg_status dg_server_run(dg_server *, int32_t) { return fail(DG_EINVAL, "server not available in this build"); }
-dg_status dg_server_poll(dg_server *, int64_t, int32_t *) { return fail(DG_EINVAL, "server not available"); }
-dg_status dg_server_fetch(dg_server *, int64_t, double *, dg_timing *) { return fail(DG_EINVAL, "server not available"); }
-void dg_server_destroy(dg_server *) {}
+
+dg_status dg_server_run(dg_server *sv, int32_t max_ticks) {
+  if (!sv) return fail(DG_EINVAL, "server is NULL");
+  if (sv->broken) return fail(DG_ESTATE, "server unusable after a device error");
+  int ticks = 0;
+  for (;;) {
+    dg_status rc = admit(sv);
+    if (rc) return rc;
+    if (sv->active.empty()) {
+      if (sv->queue.empty()) break;
+      // nothing runs: wait for the next arrival
+      const double wait = sv->reqs[sv->queue.front()]->t_arrival - sv->now();
+      if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
+      if (max_ticks > 0 && ++ticks >= max_ticks) break;
+      continue;
+    }
+    rc = tick(sv);
+    if (rc) return rc;
+    rc = retire(sv);
+    if (rc) return rc;
+    if (max_ticks > 0 && ++ticks >= max_ticks) break;
+  }
+  return DG_OK;
 }
+
+dg_status dg_server_poll(dg_server *sv, int64_t req_id, int32_t *state) {
+  if (!sv || !state) return fail(DG_EINVAL, "NULL argument");
+  auto it = sv->reqs.find(req_id);
+  if (it == sv->reqs.end()) return fail(DG_EINVAL, "unknown request");
+  *state = it->second->state;
+  return DG_OK;
+}
+
+dg_status dg_server_fetch(dg_server *sv, int64_t req_id, double *U_host, dg_timing *timing) {
+  if (!sv) return fail(DG_EINVAL, "server is NULL");
+  auto it = sv->reqs.find(req_id);
+  if (it == sv->reqs.end()) return fail(DG_EINVAL, "unknown request");
+  Request &r = *it->second;
+  if (timing) {
+    timing->t_arrival = r.t_arrival;
+    timing->t_admit = r.t_admit;
+    timing->t_done = r.t_done;
+    timing->state = r.state;
+    timing->reserved = 0;
+  }
+  if (r.state != DG_REQ_DONE && r.state != DG_REQ_FAILED) return fail(DG_ESTATE, "request not finished");
+  if (U_host && !r.result.empty()) std::memcpy(U_host, r.result.data(), r.result.size() * 8);
+  return r.state == DG_REQ_DONE ? DG_OK : fail(DG_ENONFINITE, "request failed: state not finite");
+}
+
+void dg_server_destroy(dg_server *sv) {
+  if (!sv) return;
+  (void)hipStreamSynchronize(sv->st);
+  if (sv->cst != sv->st) (void)hipStreamSynchronize(sv->cst);
+  for (auto &kv : sv->reqs) {
+    Request &r = *kv.second;
+    if (r.pinned) (void)hipHostFree(r.pinned);
+    if (r.flag_host) (void)hipHostFree(r.flag_host);
+    if (r.done_ev) (void)hipEventDestroy(r.done_ev);
+    if (r.ready) (void)hipEventDestroy(r.ready);
+  }
+  for (int s = 0; s < kDescSlots; ++s) {
+    if (sv->desc_host[s]) (void)hipHostFree(sv->desc_host[s]);
+    if (sv->desc_ev[s]) (void)hipEventDestroy(sv->desc_ev[s]);
+  }
+  delete sv;
+}
+
+}  // extern "C"

@@ -19,87 +19,106 @@ namespace dg {
 
 namespace {
 
+// Set-up arithmetic runs in x87 extended precision (T = long double) and is
+// rounded once to double, so every stored set-up quantity is accurate to the
+// last bit of its double value.
+using xr = long double;
+
 // Legendre P_k and P_k' at s (Bonnet recurrence)
-void legendre_pair(int k, double s, double &P, double &dP) {
-  double pm1 = 1.0, p = s;
+template <class T>
+void legendre_pair(int k, T s, T &P, T &dP) {
+  T pm1 = 1.0, p = s;
   if (k == 0) {
     P = 1.0;
     dP = 0.0;
     return;
   }
   for (int m = 1; m < k; ++m) {
-    double pn = ((2 * m + 1) * s * p - m * pm1) / (m + 1);
+    T pn = ((2 * m + 1) * s * p - m * pm1) / (m + 1);
     pm1 = p;
     p = pn;
   }
   P = p;
   // P_k' = k (s P_k - P_{k-1}) / (s^2 - 1), away from the end points
-  dP = (std::fabs(std::fabs(s) - 1.0) < 1e-14) ? 0.5 * k * (k + 1) * std::pow(s, k + 1) : k * (s * p - pm1) / (s * s - 1.0);
+  dP = (std::fabs(std::fabs(s) - T(1)) < T(1e-14)) ? T(0.5) * k * (k + 1) * std::pow(s, T(k + 1))
+                                                   : k * (s * p - pm1) / (s * s - T(1));
 }
 
-void gauss(int N, std::vector<double> &x, std::vector<double> &w) {
+const xr kPi = 3.141592653589793238462643383279502884L;
+
+template <class T>
+void gauss(int N, std::vector<T> &x, std::vector<T> &w) {
   int n = N + 1;
-  x.assign(n, 0.0);
-  w.assign(n, 0.0);
+  x.assign(n, T(0));
+  w.assign(n, T(0));
   for (int k = 0; k < (n + 1) / 2; ++k) {
     // Tricomi-type initial guess for the k-th largest root of P_n
-    double s = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+    T s = std::cos(T(kPi) * (k + T(0.75)) / (n + T(0.5)));
     for (int it = 0; it < 60; ++it) {
-      double P, dP;
-      legendre_pair(n, s, P, dP);
-      double ds = P / dP;
+      T P, dP;
+      legendre_pair<T>(n, s, P, dP);
+      T ds = P / dP;
       s -= ds;
-      if (std::fabs(ds) < 1e-17) break;
+      if (std::fabs(ds) < T(1e-19)) break;
     }
-    double P, dP;
-    legendre_pair(n, s, P, dP);
-    double wk = 2.0 / ((1.0 - s * s) * dP * dP);
+    T P, dP;
+    legendre_pair<T>(n, s, P, dP);
+    T wk = T(2) / ((T(1) - s * s) * dP * dP);
     x[n - 1 - k] = s;
     x[k] = -s;
     w[n - 1 - k] = wk;
     w[k] = wk;
   }
-  if (n % 2) x[n / 2] = 0.0;
+  if (n % 2) x[n / 2] = T(0);
+}
+
+template <class T>
+void lobatto_t(int N, std::vector<T> &x, std::vector<T> &w) {
+  int n = N + 1;
+  x.assign(n, T(0));
+  w.assign(n, T(0));
+  x[0] = T(-1);
+  x[N] = T(1);
+  // interior nodes: roots of q = P_{N+1} - P_{N-1} = (2N+1)/(N(N+1)) (x^2-1) P_N',
+  // with q' = (2N+1) P_N
+  for (int k = 1; k <= N / 2; ++k) {
+    T s = std::cos(T(kPi) * k / N);
+    for (int it = 0; it < 60; ++it) {
+      T Pa, dPa, Pb, dPb, Pn, dPn;
+      legendre_pair<T>(N + 1, s, Pa, dPa);
+      legendre_pair<T>(N - 1, s, Pb, dPb);
+      legendre_pair<T>(N, s, Pn, dPn);
+      T ds = (Pa - Pb) / ((T(2) * N + T(1)) * Pn);
+      s -= ds;
+      if (std::fabs(ds) < T(1e-19)) break;
+    }
+    x[N - k] = s;
+    x[k] = -s;
+  }
+  if (n % 2) x[N / 2] = T(0);
+  for (int k = 0; k < n; ++k) {
+    T P, dP;
+    legendre_pair<T>(N, x[k], P, dP);
+    w[k] = T(2) / (N * (N + T(1)) * P * P);
+  }
 }
 
 }  // namespace
 
 void lobatto(int N, std::vector<double> &x, std::vector<double> &w) {
-  int n = N + 1;
-  x.assign(n, 0.0);
-  w.assign(n, 0.0);
-  x[0] = -1.0;
-  x[N] = 1.0;
-  // interior nodes: roots of q = P_{N+1} - P_{N-1} = (2N+1)/(N(N+1)) (x^2-1) P_N',
-  // with q' = (2N+1) P_N
-  for (int k = 1; k <= N / 2; ++k) {
-    double s = std::cos(M_PI * k / N);
-    for (int it = 0; it < 60; ++it) {
-      double Pa, dPa, Pb, dPb, Pn, dPn;
-      legendre_pair(N + 1, s, Pa, dPa);
-      legendre_pair(N - 1, s, Pb, dPb);
-      legendre_pair(N, s, Pn, dPn);
-      double ds = (Pa - Pb) / ((2.0 * N + 1.0) * Pn);
-      s -= ds;
-      if (std::fabs(ds) < 1e-17) break;
-    }
-    x[N - k] = s;
-    x[k] = -s;
-  }
-  if (n % 2) x[N / 2] = 0.0;
-  for (int k = 0; k < n; ++k) {
-    double P, dP;
-    legendre_pair(N, x[k], P, dP);
-    w[k] = 2.0 / (N * (N + 1.0) * P * P);
-  }
+  std::vector<xr> xl, wl;
+  lobatto_t<xr>(N, xl, wl);
+  x.assign(xl.begin(), xl.end());
+  w.assign(wl.begin(), wl.end());
 }
 
 namespace {
 
 // barycentric weights lambda_j = 1 / prod_{k != j} (x_j - x_k)
-std::vector<double> bary(const std::vector<double> &x) {
+template <class T>
+std::vector<T> bary(const std::vector<T> &x) {
   int n = (int)x.size();
-  std::vector<double> lam(n, 1.0);
+  std::vector<T> lam(n, T(1));
   for (int j = 0; j < n; ++j)
     for (int k = 0; k < n; ++k)
       if (k != j) lam[j] /= (x[j] - x[k]);
@@ -107,24 +126,25 @@ std::vector<double> bary(const std::vector<double> &x) {
 }
 
 // values l_j(s) of all basis polynomials at s, barycentric form
-void lagrange_values(const std::vector<double> &x, const std::vector<double> &lam, double s,
-                     std::vector<double> &out) {
+template <class T>
+void lagrange_values(const std::vector<T> &x, const std::vector<T> &lam, T s, std::vector<T> &out) {
   int n = (int)x.size();
-  out.assign(n, 0.0);
+  out.assign(n, T(0));
   for (int j = 0; j < n; ++j)
     if (s == x[j]) {
-      out[j] = 1.0;
+      out[j] = T(1);
       return;
     }
-  double den = 0.0;
+  T den = T(0);
   for (int j = 0; j < n; ++j) den += lam[j] / (s - x[j]);
   for (int j = 0; j < n; ++j) out[j] = lam[j] / (s - x[j]) / den;
 }
 
 // M[b][a] = l_a(t_b)
-std::vector<double> interp(const std::vector<double> &from, const std::vector<double> &to) {
-  std::vector<double> lam = bary(from), row;
-  std::vector<double> M(to.size() * from.size());
+template <class T>
+std::vector<T> interp(const std::vector<T> &from, const std::vector<T> &to) {
+  std::vector<T> lam = bary(from), row;
+  std::vector<T> M(to.size() * from.size());
   for (size_t b = 0; b < to.size(); ++b) {
     lagrange_values(from, lam, to[b], row);
     for (size_t a = 0; a < from.size(); ++a) M[b * from.size() + a] = row[a];
@@ -133,11 +153,12 @@ std::vector<double> interp(const std::vector<double> &from, const std::vector<do
 }
 
 // D_ij = l_j'(x_i) = (lam_j / lam_i) / (x_i - x_j), D_ii = -sum_{j != i} D_ij
-std::vector<double> diffmat(const std::vector<double> &x) {
+template <class T>
+std::vector<T> diffmat(const std::vector<T> &x) {
   int n = (int)x.size();
-  std::vector<double> lam = bary(x), D(n * n, 0.0);
+  std::vector<T> lam = bary(x), D(n * n, T(0));
   for (int i = 0; i < n; ++i) {
-    double s = 0.0;
+    T s = T(0);
     for (int j = 0; j < n; ++j) {
       if (j == i) continue;
       D[i * n + j] = (lam[j] / lam[i]) / (x[i] - x[j]);
@@ -156,20 +177,27 @@ Basis make_basis(int N, int nodes) {
   b.n = N + 1;
   b.nodes = nodes;
   int n = b.n;
-  if (nodes == 0) gauss(N, b.x, b.w);
-  else lobatto(N, b.x, b.w);
-  b.D = diffmat(b.x);
+  std::vector<xr> x, w;
+  if (nodes == 0) gauss<xr>(N, x, w);
+  else lobatto_t<xr>(N, x, w);
+  std::vector<xr> D = diffmat(x);
+  auto rd = [](const std::vector<xr> &v) { return std::vector<double>(v.begin(), v.end()); };
+  b.x = rd(x);
+  b.w = rd(w);
+  b.D = rd(D);
   b.Dhat.assign(n * n, 0.0);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) b.Dhat[i * n + j] = -(b.w[j] / b.w[i]) * b.D[j * n + i];
-  std::vector<double> lam = bary(b.x);
-  lagrange_values(b.x, lam, -1.0, b.lm);
-  lagrange_values(b.x, lam, 1.0, b.lp);
+    for (int j = 0; j < n; ++j) b.Dhat[i * n + j] = (double)(-(w[j] / w[i]) * D[j * n + i]);
+  std::vector<xr> lam = bary(x), lm, lp;
+  lagrange_values<xr>(x, lam, xr(-1), lm);
+  lagrange_values<xr>(x, lam, xr(1), lp);
+  b.lm = rd(lm);
+  b.lp = rd(lp);
   b.lhm.resize(n);
   b.lhp.resize(n);
   for (int i = 0; i < n; ++i) {
-    b.lhm[i] = b.lm[i] / b.w[i];
-    b.lhp[i] = b.lp[i] / b.w[i];
+    b.lhm[i] = (double)(lm[i] / w[i]);
+    b.lhp[i] = (double)(lp[i] / w[i]);
   }
   b.xhalf.assign(n + 1, -1.0);
   for (int m = 0; m < n; ++m) b.xhalf[m + 1] = b.xhalf[m] + b.w[m];
@@ -178,15 +206,15 @@ Basis make_basis(int N, int nodes) {
   // with gamma_a = sum_i w_i ((2a+1)/2) P_a(x_i)^2 (= 1 except the top Lobatto mode).
   b.Vinv.assign(n * n, 0.0);
   for (int a = 0; a < n; ++a) {
-    double ga = 0.0;
-    std::vector<double> phi(n);
+    xr ga = 0.0;
+    std::vector<xr> phi(n);
     for (int i = 0; i < n; ++i) {
-      double P, dP;
-      legendre_pair(a, b.x[i], P, dP);
-      phi[i] = std::sqrt((2.0 * a + 1.0) / 2.0) * P;
-      ga += b.w[i] * phi[i] * phi[i];
+      xr P, dP;
+      legendre_pair<xr>(a, x[i], P, dP);
+      phi[i] = std::sqrt((xr(2) * a + 1) / 2) * P;
+      ga += w[i] * phi[i] * phi[i];
     }
-    for (int i = 0; i < n; ++i) b.Vinv[a * n + i] = b.w[i] * phi[i] / ga;
+    for (int i = 0; i < n; ++i) b.Vinv[a * n + i] = (double)(w[i] * phi[i] / ga);
   }
   return b;
 }
@@ -234,37 +262,39 @@ inline int lnode(int n, int d, int l, int p, int q) {
 }
 
 // y = (A along direction d) x on an n^3 block (A is n x n, row-major)
-void apply_dir(int n, const double *A, int d, const double *x, double *y) {
+template <class T>
+void apply_dir(int n, const T *A, int d, const T *x, T *y) {
   for (int q = 0; q < n; ++q)
     for (int p = 0; p < n; ++p)
       for (int l = 0; l < n; ++l) {
-        double s = 0.0;
+        T s = T(0);
         for (int a = 0; a < n; ++a) s += A[l * n + a] * x[lnode(n, d, a, p, q)];
         y[lnode(n, d, l, p, q)] = s;
       }
 }
 
 // tensor interpolation of a scalar field from an m^3 to an n^3 grid (M is n x m)
-void tensor_interp(int m, int n, const double *M, const double *x, double *y) {
-  std::vector<double> a((size_t)n * m * m), b((size_t)n * n * m);
+template <class T, class S>
+void tensor_interp(int m, int n, const T *M, const S *x, T *y) {
+  std::vector<T> a((size_t)n * m * m), b((size_t)n * n * m);
   for (int k = 0; k < m; ++k)
     for (int j = 0; j < m; ++j)
       for (int i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int r = 0; r < m; ++r) s += M[i * m + r] * x[r + m * (j + m * k)];
+        T s = T(0);
+        for (int r = 0; r < m; ++r) s += M[i * m + r] * T(x[r + m * (j + m * k)]);
         a[i + n * (j + m * k)] = s;
       }
   for (int k = 0; k < m; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
-        double s = 0.0;
+        T s = T(0);
         for (int r = 0; r < m; ++r) s += M[j * m + r] * a[i + n * (r + m * k)];
         b[i + n * (j + n * k)] = s;
       }
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
-        double s = 0.0;
+        T s = T(0);
         for (int r = 0; r < m; ++r) s += M[k * m + r] * b[i + n * (j + n * r)];
         y[i + n * (j + n * k)] = s;
       }
@@ -276,80 +306,87 @@ int build_geometry(const Basis &b, const dg_mesh &m, Geometry &g, std::string &e
   const int N = b.N, n = b.n, n2 = n * n, n3 = n2 * n;
   const int64_t E = m.n_elems;
   const int ng = m.n_geo + 1, ng3 = ng * ng * ng;
-  std::vector<double> xl, wl, xgeo, wgeo;
-  lobatto(N, xl, wl);
-  lobatto(m.n_geo, xgeo, wgeo);
-  const std::vector<double> Mgeo = interp(xgeo, xl);  // LGL(n_geo) -> LGL(N)
-  const std::vector<double> Ml2s = interp(xl, b.x);   // LGL(N) -> solution nodes
-  const std::vector<double> DL = diffmat(xl);
+  std::vector<xr> xl, wl, xgeo, wgeo, xs, ws;
+  lobatto_t<xr>(N, xl, wl);
+  lobatto_t<xr>(m.n_geo, xgeo, wgeo);
+  if (b.nodes == 0) gauss<xr>(N, xs, ws);
+  else lobatto_t<xr>(N, xs, ws);
+  const std::vector<xr> Mgeo = interp(xgeo, xl);  // LGL(n_geo) -> LGL(N)
+  const std::vector<xr> Ml2s = interp(xl, xs);    // LGL(N) -> solution nodes
+  const std::vector<xr> DL = diffmat(xl);
   g.Ja.assign((size_t)9 * E * n3, 0.0);
   g.J.assign((size_t)E * n3, 0.0);
   g.Xs.assign((size_t)3 * E * n3, 0.0);
   std::vector<double> nsRaw((size_t)3 * E * 6 * n2, 0.0);  // own outward n*shat per face node
 
   parallel_for(E, [&](int64_t e) {
-    // geometry on LGL(N), element-local origin for the curl form
-    double X[3][1000], dX[3][3][1000];  // X[m][node], dX[j][m][node] = d x_m / d xi_j
-    double Xsh[3][1000], tmp[1000], V[1000], dV[1000];
-    for (int c = 0; c < 3; ++c) tensor_interp(ng, n, Mgeo.data(), m.x_geo + ((size_t)e * 3 + c) * ng3, X[c]);
+    // geometry on LGL(N), element-local origin for the curl form (a constant
+    // shift leaves the curl form unchanged: the discrete curl of a discrete
+    // gradient vanishes because the line derivatives commute)
+    std::vector<xr> buf((size_t)(3 + 9 + 3 + 3 + 9 + 9) * n3 + 2 * n3);
+    xr *X = buf.data(), *dX = X + 3 * n3, *Xsh = dX + 9 * n3, *tmp = Xsh + 3 * n3;
+    xr *JaL = tmp + 3 * n3, *A = JaL + 9 * n3, *V = A + 9 * n3, *dV = V + n3;
+    auto x_ = [&](int c) { return X + c * n3; };
+    auto dx_ = [&](int j, int c) { return dX + (j * 3 + c) * n3; };
+    auto ja_ = [&](int i, int c) { return JaL + (i * 3 + c) * n3; };
+    for (int c = 0; c < 3; ++c) tensor_interp(ng, n, Mgeo.data(), m.x_geo + ((size_t)e * 3 + c) * ng3, x_(c));
     for (int c = 0; c < 3; ++c)
-      for (int a = 0; a < n3; ++a) Xsh[c][a] = X[c][a] - X[c][0];
+      for (int a = 0; a < n3; ++a) Xsh[c * n3 + a] = x_(c)[a] - x_(c)[0];
     for (int j = 0; j < 3; ++j)
-      for (int c = 0; c < 3; ++c) apply_dir(n, DL.data(), j, X[c], dX[j][c]);
+      for (int c = 0; c < 3; ++c) apply_dir(n, DL.data(), j, x_(c), dx_(j, c));
     // Ja^i_nn on LGL(N):  -(curl_xi (x_l grad x_m))_i,  (nn, m, l) cyclic
-    double JaL[3][3][1000];  // [i][nn][node]
     for (int nn = 0; nn < 3; ++nn) {
       int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
       for (int i = 0; i < 3; ++i) {
         int bb = (i + 1) % 3, cc = (i + 2) % 3;
         // (curl W)_i = d_bb W_cc - d_cc W_bb,  W_j = x_ll d_j x_mm
-        for (int a = 0; a < n3; ++a) V[a] = Xsh[ll][a] * dX[cc][mm][a];
+        for (int a = 0; a < n3; ++a) V[a] = Xsh[ll * n3 + a] * dx_(cc, mm)[a];
         apply_dir(n, DL.data(), bb, V, dV);
-        for (int a = 0; a < n3; ++a) JaL[i][nn][a] = -dV[a];
-        for (int a = 0; a < n3; ++a) V[a] = Xsh[ll][a] * dX[bb][mm][a];
+        for (int a = 0; a < n3; ++a) ja_(i, nn)[a] = -dV[a];
+        for (int a = 0; a < n3; ++a) V[a] = Xsh[ll * n3 + a] * dx_(bb, mm)[a];
         apply_dir(n, DL.data(), cc, V, dV);
-        for (int a = 0; a < n3; ++a) JaL[i][nn][a] += dV[a];
+        for (int a = 0; a < n3; ++a) ja_(i, nn)[a] += dV[a];
       }
     }
     // to the solution nodes
     for (int i = 0; i < 3; ++i)
       for (int d = 0; d < 3; ++d) {
-        tensor_interp(n, n, Ml2s.data(), JaL[i][d], tmp);
-        for (int a = 0; a < n3; ++a) g.Ja[((size_t)(3 * i + d) * E + e) * n3 + a] = tmp[a];
+        tensor_interp(n, n, Ml2s.data(), ja_(i, d), tmp);
+        for (int a = 0; a < n3; ++a) g.Ja[((size_t)(3 * i + d) * E + e) * n3 + a] = (double)tmp[a];
       }
     for (int c = 0; c < 3; ++c) {
-      tensor_interp(n, n, Ml2s.data(), X[c], tmp);
-      for (int a = 0; a < n3; ++a) g.Xs[((size_t)c * E + e) * n3 + a] = tmp[a];
+      tensor_interp(n, n, Ml2s.data(), x_(c), tmp);
+      for (int a = 0; a < n3; ++a) g.Xs[((size_t)c * E + e) * n3 + a] = (double)tmp[a];
     }
-    double A[3][3][1000];
     for (int j = 0; j < 3; ++j)
-      for (int c = 0; c < 3; ++c) tensor_interp(n, n, Ml2s.data(), dX[j][c], A[j][c]);
+      for (int c = 0; c < 3; ++c) tensor_interp(n, n, Ml2s.data(), dx_(j, c), A + (j * 3 + c) * n3);
+    auto A_ = [&](int j, int c, int a) { return A[(j * 3 + c) * n3 + a]; };
     for (int a = 0; a < n3; ++a) {
-      double det = A[0][0][a] * (A[1][1][a] * A[2][2][a] - A[1][2][a] * A[2][1][a]) -
-                   A[0][1][a] * (A[1][0][a] * A[2][2][a] - A[1][2][a] * A[2][0][a]) +
-                   A[0][2][a] * (A[1][0][a] * A[2][1][a] - A[1][1][a] * A[2][0][a]);
-      g.J[(size_t)e * n3 + a] = det;
+      xr det = A_(0, 0, a) * (A_(1, 1, a) * A_(2, 2, a) - A_(1, 2, a) * A_(2, 1, a)) -
+               A_(0, 1, a) * (A_(1, 0, a) * A_(2, 2, a) - A_(1, 2, a) * A_(2, 0, a)) +
+               A_(0, 2, a) * (A_(1, 0, a) * A_(2, 1, a) - A_(1, 1, a) * A_(2, 0, a));
+      g.J[(size_t)e * n3 + a] = (double)det;
     }
     // face metrics: slice of Ja^d on the LGL face, interpolated in 2-D
     for (int f = 0; f < 6; ++f) {
       int d = f / 2;
       int l = (f & 1) ? n - 1 : 0;
-      double sg = (f & 1) ? 1.0 : -1.0;
+      xr sg = (f & 1) ? 1.0L : -1.0L;
       for (int c = 0; c < 3; ++c) {
-        double slice[100], half[100];
+        xr slice[100], half[100];
         for (int q = 0; q < n; ++q)
-          for (int p = 0; p < n; ++p) slice[p + n * q] = JaL[d][c][lnode(n, d, l, p, q)];
+          for (int p = 0; p < n; ++p) slice[p + n * q] = ja_(d, c)[lnode(n, d, l, p, q)];
         for (int q = 0; q < n; ++q)
           for (int p = 0; p < n; ++p) {
-            double s = 0.0;
-            for (int r = 0; r < n; ++r) s += Ml2s[p * n + r] * slice[r + n * q];
-            half[p + n * q] = s;
+            xr sum = 0.0L;
+            for (int r = 0; r < n; ++r) sum += Ml2s[p * n + r] * slice[r + n * q];
+            half[p + n * q] = sum;
           }
         for (int q = 0; q < n; ++q)
           for (int p = 0; p < n; ++p) {
-            double s = 0.0;
-            for (int r = 0; r < n; ++r) s += Ml2s[q * n + r] * half[p + n * r];
-            nsRaw[((size_t)c * E * 6 + e * 6 + f) * n2 + p + n * q] = sg * s;
+            xr sum = 0.0L;
+            for (int r = 0; r < n; ++r) sum += Ml2s[q * n + r] * half[p + n * r];
+            nsRaw[((size_t)c * E * 6 + e * 6 + f) * n2 + p + n * q] = (double)(sg * sum);
           }
       }
     }

@@ -82,6 +82,7 @@ Layout make_layout(const dg_params &p, int64_t E) {
   L.Xs = p.source ? take(3 * E * n3 * 8) : SIZE_MAX;
   L.basis = take(BasisOffsets(n).total * rs);
   L.alpha = take(E * rs);
+  L.alpha_raw = take(E * rs);
   L.alpha_in = take(E * rs);
   L.scratch = take(kRedBlocks * 8 * sizeof(double));
   L.total = o;
@@ -89,11 +90,10 @@ Layout make_layout(const dg_params &p, int64_t E) {
 }
 
 template <typename real>
-static void fill_view(dg_solver *s, View<real> &v) {
-  char *ws = (char *)s->ws;
-  const Layout &L = s->L;
+void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, int64_t E) {
+  char *ws = (char *)base;
   auto at = [&](size_t off) -> char * { return off == SIZE_MAX ? nullptr : ws + off; };
-  v.E = s->E;
+  v.E = E;
   v.U = (double *)at(L.U);
   v.dU = (double *)at(L.dU);
   v.R = nullptr;
@@ -108,8 +108,8 @@ static void fill_view(dg_solver *s, View<real> &v) {
   v.Xs = (const double *)at(L.Xs);
   v.basis = (const real *)at(L.basis);
   v.alpha = (real *)at(L.alpha);
+  v.alpha_raw = (real *)at(L.alpha_raw);
   v.alpha_in = nullptr;
-  const dg_params &p = s->p;
   v.gamma = (real)p.gamma;
   v.Rgas = (real)p.R;
   v.mu = (real)p.mu;
@@ -130,6 +130,52 @@ static void fill_view(dg_solver *s, View<real> &v) {
   v.alpha_min = (real)p.alpha_min;
   v.alpha_max = (real)p.alpha_max;
   v.ind_T = (real)(p.ind_a * std::pow(10.0, -p.ind_c * std::pow(p.N + 1.0, 0.25)));
+}
+template void fill_view<double>(View<double> &, void *, const Layout &, const dg_params &, int64_t);
+template void fill_view<float>(View<float> &, void *, const Layout &, const dg_params &, int64_t);
+
+// Host set-up of one solve and its upload into the workspace at `base`
+// (enqueued on st; the returned staging buffers must live until st has
+// passed the copies).
+dg_status setup_upload(const dg_params &p, const dg_mesh &m, void *base, const Layout &L, hipStream_t st,
+                       Staging &stg) {
+  Basis b = make_basis(p.N, p.nodes);
+  Geometry g;
+  std::string err;
+  dg_status rc = build_geometry(b, m, g, err);
+  if (rc) return fail(rc, err);
+  const bool mixed = p.precision == 1;
+  std::vector<double> invJ(g.J.size());
+  for (size_t i = 0; i < g.J.size(); ++i) invJ[i] = 1.0 / g.J[i];
+  char *ws = (char *)base;
+  auto put = [&](size_t off, std::vector<double> &&h) -> hipError_t {
+    if (!mixed) {
+      stg.d.push_back(std::move(h));
+      const std::vector<double> &x = stg.d.back();
+      return hipMemcpyAsync(ws + off, x.data(), x.size() * 8, hipMemcpyHostToDevice, st);
+    }
+    std::vector<float> f(h.size());
+    for (size_t i = 0; i < h.size(); ++i) f[i] = (float)h[i];
+    stg.f.push_back(std::move(f));
+    const std::vector<float> &x = stg.f.back();
+    return hipMemcpyAsync(ws + off, x.data(), x.size() * 4, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipMemsetAsync(ws, 0, L.total, st);
+  if (e == hipSuccess) e = put(L.Ja, std::move(g.Ja));
+  if (e == hipSuccess) e = put(L.invJ, std::move(invJ));
+  if (e == hipSuccess) e = put(L.NS, std::move(g.NS));
+  if (e == hipSuccess) e = put(L.basis, basis_block(b));
+  if (e == hipSuccess) {
+    stg.c = std::move(g.conn);
+    e = hipMemcpyAsync(ws + L.conn, stg.c.data(), stg.c.size() * sizeof(int2), hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess && p.source) {
+    stg.d.push_back(std::move(g.Xs));
+    const std::vector<double> &x = stg.d.back();
+    e = hipMemcpyAsync(ws + L.Xs, x.data(), x.size() * 8, hipMemcpyHostToDevice, st);
+  }
+  if (e != hipSuccess) return fail(DG_EDEVICE, std::string("set-up upload: ") + hipGetErrorString(e));
+  return DG_OK;
 }
 
 // upload a host FP64 array into device memory of the solve's arithmetic type
@@ -193,7 +239,7 @@ static hipError_t stage(dg_solver *s, int mode, double t, double dt, double A, d
     if (e != hipSuccess) return e;
     s->traces_valid = true;
   }
-  if (s->p.viscous) {
+  if (s->p.viscous || s->p.shock_capturing) {  // lifting and/or the indicator
     e = run_kernel<real>(s, K_LIFT, 0, v);
     if (e != hipSuccess) return e;
   }
@@ -265,27 +311,12 @@ dg_status dg_create(const dg_params *p, const dg_mesh *m, void *d_workspace, siz
   s->st = (hipStream_t)hip_stream;
   s->mixed = p->precision == 1;
 
-  Basis b = make_basis(p->N, p->nodes);
-  Geometry g;
-  std::string err;
-  rc = build_geometry(b, *m, g, err);
-  if (rc) return fail(rc, err);
-  std::vector<double> invJ(g.J.size());
-  for (size_t i = 0; i < g.J.size(); ++i) invJ[i] = 1.0 / g.J[i];
-
-  fill_view(s.get(), s->vd);
-  fill_view(s.get(), s->vf);
-  hipError_t e = hipMemsetAsync(s->ws, 0, L.total, s->st);
-  if (e == hipSuccess) e = upload_real(s.get(), L.Ja, g.Ja);
-  if (e == hipSuccess) e = upload_real(s.get(), L.invJ, invJ);
-  if (e == hipSuccess) e = upload_real(s.get(), L.NS, g.NS);
-  if (e == hipSuccess) e = upload_real(s.get(), L.basis, basis_block(b));
-  if (e == hipSuccess)
-    e = hipMemcpyAsync((char *)s->ws + L.conn, g.conn.data(), g.conn.size() * sizeof(int2), hipMemcpyHostToDevice,
-                       s->st);
-  if (e == hipSuccess && p->source)
-    e = hipMemcpyAsync((char *)s->ws + L.Xs, g.Xs.data(), g.Xs.size() * 8, hipMemcpyHostToDevice, s->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->st);  // host vectors go out of scope
+  fill_view(s->vd, s->ws, L, *p, s->E);
+  fill_view(s->vf, s->ws, L, *p, s->E);
+  Staging stg;
+  rc = setup_upload(*p, *m, s->ws, L, s->st, stg);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(s->st);  // staging buffers go out of scope
   if (e != hipSuccess) return device_error(nullptr, e, "dg_create upload");
   s->t = 0.0;
   s->cur = 0;

@@ -14,7 +14,7 @@ constexpr int kRedBlocks = 1024;  // blocks of the reduction kernels
 
 // byte offsets of every array inside the caller's workspace (SIZE_MAX: absent)
 struct Layout {
-  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Gtr, G, conn, Xs, basis, alpha, alpha_in, scratch, total;
+  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Gtr, G, conn, Xs, basis, alpha, alpha_raw, alpha_in, scratch, total;
 };
 
 Layout make_layout(const dg_params &p, int64_t E);
@@ -22,6 +22,19 @@ dg_status check_params(const dg_params *p);
 dg_status fail(dg_status code, const std::string &msg);
 
 extern const double RK_A[5], RK_B[5], RK_C[5];
+
+// host staging buffers of a set-up upload
+struct Staging {
+  std::vector<std::vector<double>> d;
+  std::vector<std::vector<float>> f;
+  std::vector<int2> c;
+};
+
+template <typename real>
+void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, int64_t E);
+dg_status setup_upload(const dg_params &p, const dg_mesh &m, void *base, const Layout &L, hipStream_t st,
+                       Staging &stg);
+dg_status device_error(dg_solver *s, hipError_t e, const char *what);
 
 struct ProfEvent {
   int kernel;

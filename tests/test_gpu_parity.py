@@ -73,8 +73,13 @@ CASES = ["mms_k4_n3", "tgv_curved_rot_k3_n7", "tgv_curved_k2_n5_llf", "ragged_n3
 
 @pytest.mark.parametrize("name", CASES)
 def test_rhs_parity(name):
-    """one evaluation of the time derivative; the TGV cases carry the p0 ~ 71
-    background whose gradients cancel, hence the looser bound there"""
+    """one evaluation of the time derivative.  The TGV cases carry the
+    background pressure p0 = 71.4 whose gradient must cancel: the two sides
+    compute the metric terms independently, each to round-off (~1e-14
+    relative), and p0 times that difference, differentiated, is ~2e-11 against
+    |R| ~ 0.06 -- measured: the freestream residuals of the two sides differ by
+    2e-10 of |R| on the 3^3 mesh (at Ma = 1, p0 = 0.71, parity is 4e-12).
+    Hence 1e-9 there; 1e-12 where the background is O(1)."""
     wl = _case(name)
     _say(f"[rhs parity] {name} E={wl.mesh.n_elems} N={wl.params['N']}")
     o = O.Oracle(wl.params, wl.mesh)
@@ -83,7 +88,8 @@ def test_rhs_parity(name):
     t = 0.13
     R_gpu = s.rhs(t)
     R_orc = o.rhs(wl.U0, t)
-    tol = 1e-10 if name.startswith("tgv") else 1e-12
+    tol = 1e-9 if name.startswith("tgv") else 1e-12
+    _say(f"  rel L2 {rel(R_gpu, R_orc):.3e}")
     assert rel(R_gpu, R_orc) <= tol, rel(R_gpu, R_orc)
 
 
@@ -142,7 +148,8 @@ def test_full_size_tgv_24cubed_one_step():
     s.set_state(wl.U0, 0.0)
     R_gpu = s.rhs(0.0)
     R_orc = o.rhs(wl.U0, 0.0)
-    assert rel(R_gpu, R_orc) <= 1e-10
+    _say(f"  rhs rel L2 {rel(R_gpu, R_orc):.3e}")
+    assert rel(R_gpu, R_orc) <= 1e-9
     del R_gpu, R_orc
     dt = s.stable_dt(0.9, 0.9)
     assert abs(dt / o.stable_dt(wl.U0) - 1.0) < 1e-12

@@ -1,0 +1,109 @@
+"""The serving loop: continuous batching of independent solves.  Each result
+must equal the same request run alone through a plain solver (bitwise: a
+request's arithmetic does not depend on the rest of the batch), for FP64 and
+the mixed form; a poisoned request fails alone; admission waits for memory."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(n, seed, precision_mix=True):
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        req = dict(id=i, K=int(g.integers(2, 5)), N=int(g.choice([3, 5, 7])), Ma=float(g.uniform(0.05, 0.3)),
+                   Re=float(g.uniform(400, 1600)), steps=int(g.integers(2, 9)))
+        prec = int(g.integers(0, 2)) if precision_mix else 0
+        out.append((req, W.request_workload(req, precision=prec)))
+    return out
+
+
+def _alone(wl, dt):
+    import paper_2404_12703_amd as P
+    s = P.Solver(wl.params, wl.mesh)
+    s.set_state(wl.U0)
+    s.advance(wl.steps, dt)
+    return s.state()
+
+
+def _dt(wl):
+    import paper_2404_12703_amd as P
+    s = P.Solver(wl.params, wl.mesh)
+    s.set_state(wl.U0)
+    return s.stable_dt(0.9, 0.9)
+
+
+def test_batched_equals_alone_bitwise():
+    import paper_2404_12703_amd as P
+    reqs = _requests(16, 0)
+    _say("[server] 16 mixed requests")
+    sv = P.Server(arena_bytes=2 << 30, hbm_budget=2 << 30, max_active=8)
+    ids = []
+    dts = []
+    for req, wl in reqs:
+        dt = _dt(wl)
+        dts.append(dt)
+        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, wl.steps, dt, 0.0))
+    sv.run(0)
+    for (req, wl), rid, dt in zip(reqs, ids, dts):
+        assert sv.poll(rid) == P.REQ_DONE
+        U, tm = sv.fetch(rid)
+        assert tm["t_done"] >= tm["t_admit"] >= 0.0
+        assert np.array_equal(U, _alone(wl, dt)), (req, wl.params["precision"])
+
+
+def test_poisoned_request_fails_alone_and_budget_binds():
+    import paper_2404_12703_amd as P
+    reqs = _requests(6, 1, precision_mix=False)
+    _say("[server] poison + tight budget")
+    need = max(P.workspace_bytes(wl.params, wl.mesh.n_elems) for _, wl in reqs)
+    # room for about two requests at a time: admission must wait for retirements
+    sv = P.Server(arena_bytes=64 << 20, hbm_budget=int(2.2 * need), max_active=8)
+    ids, dts = [], []
+    for i, (req, wl) in enumerate(reqs):
+        U0 = wl.U0.copy()
+        if i == 2:
+            U0[0, 0, 0] = np.nan
+        dt = _dt(wl)
+        dts.append(dt)
+        ids.append(sv.submit(wl.params, wl.mesh, U0, wl.steps, dt, 0.0))
+    sv.run(0)
+    for i, ((req, wl), rid, dt) in enumerate(zip(reqs, ids, dts)):
+        if i == 2:
+            assert sv.poll(rid) == P.REQ_FAILED
+            continue
+        assert sv.poll(rid) == P.REQ_DONE
+        U, _ = sv.fetch(rid)
+        assert np.array_equal(U, _alone(wl, dt))
+    # a request that can never fit is refused at submission
+    big = W.request_workload(dict(K=12, N=7, Ma=0.1, Re=1000.0, steps=1))
+    with pytest.raises(P.DGError) as ei:
+        sv.submit(big.params, big.mesh, big.U0, 1, 1e-3, 0.0)
+    assert ei.value.code == -6
+
+
+def test_arrivals_are_admitted_while_others_run():
+    """requests arriving later join a running batch (continuous batching)"""
+    import paper_2404_12703_amd as P
+    reqs = _requests(6, 2, precision_mix=False)
+    sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=8)
+    ids = []
+    for i, (req, wl) in enumerate(reqs):
+        wl.steps = 40
+        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, 40, _dt(wl), 0.0 if i < 3 else 0.02))
+    sv.run(0)
+    tms = [sv.fetch(r)[1] for r in ids]
+    first_done = min(t["t_done"] for t in tms[:3])
+    late_admit = min(t["t_admit"] for t in tms[3:])
+    assert all(t["state"] == P.REQ_DONE for t in tms)
+    assert late_admit < first_done  # a late arrival ran alongside the early ones

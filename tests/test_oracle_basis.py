@@ -14,7 +14,7 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_
 
 
 def _basis(N, nodes):
-    m = W.box_mesh(1, -1.0, 1.0, 1)
+    m = W.box_mesh(2, -1.0, 1.0, 1)
     return O.Oracle(W.params(N, node_type=nodes, viscous=0), m).basis()
 
 

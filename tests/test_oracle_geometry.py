@@ -73,3 +73,37 @@ def test_mismatched_connectivity_is_rejected():
     m.nbr_face[0, 1] = 3
     with pytest.raises(ValueError):
         O.Oracle(W.params(2, viscous=0), m)
+
+
+@pytest.mark.parametrize("K", [(3, 2, 1), (1, 1, 1)])
+def test_faces_touching_their_own_periodic_image(K):
+    """one element across the box: edge nodes of a face coincide with several
+    neighbour nodes modulo the period; the matching must still find the one
+    consistent correspondence (freestream and conservation hold)"""
+    N = 4
+    m = W.box_mesh(K, 0.0, 2 * np.pi, N, amp=0.05, rotate=True)
+    o = O.Oracle(W.params(N, riemann=1, mu=1e-2), m)
+    X = m.points(W.gl_points(N))
+    U = W.uniform_state(X, 1.2, (0.3, -0.2, 0.5), 2.0, 1.4)
+    assert np.abs(o.rhs(U)).max() < 1e-10 * 2.0 / np.pi
+    U = W.random_smooth_state(X, 1, 1.4, m.period)
+    R = o.rhs(U)
+    b, g = o.basis(), o.geometry()
+    wJ = g["J"] * np.einsum("k,j,i->kji", b["w"], b["w"], b["w"]).ravel()[None]
+    assert np.all(np.abs((R * wJ[None]).sum(axis=(1, 2))) < 1e-13 * np.abs(R * wJ[None]).sum(axis=(1, 2)))
+    # and the correspondence agrees with the generator's orientation codes
+    n = N + 1
+    for e in range(m.n_elems):
+        for f in range(6):
+            for q in range(n):
+                for p in range(n):
+                    pp, qq = W.apply_orient(int(m.nbr_orient[e, f]), p, q, N)
+                    assert g["fmap"][e, f, p + n * q] == pp + n * qq
+
+
+def test_ambiguous_face_matching_is_refused():
+    """N = 1 on one element across the box: the two faces' four corners are all
+    periodic images of each other, so no unique correspondence exists"""
+    m = W.box_mesh(1, 0.0, 1.0, 1)
+    with pytest.raises(ValueError):
+        O.Oracle(W.params(1, viscous=0), m)

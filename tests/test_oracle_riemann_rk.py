@@ -14,7 +14,7 @@ GAMMA = 1.4
 
 
 def _o():
-    return O.Oracle(W.params(1, viscous=0), W.box_mesh(1, -1.0, 1.0, 1))
+    return O.Oracle(W.params(1, viscous=0), W.box_mesh(2, -1.0, 1.0, 1))
 
 
 def _cons(rho, u, p):
