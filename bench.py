@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48, help="requests of the served stream")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed precision and latency")
     ap.add_argument("--only-main", action="store_true", help="time the main workload only (profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it", file=sys.stderr)
@@ -174,6 +176,18 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        copy_gbs = 10 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+        del a, b
     wl = W.tgv_workload(K=args.K, N=7, steps=args.steps)
     N = 7
     s, dt, el, prof = time_solver(P, wl, args.steps, args.warmup, profile_pass=not args.only_main)
@@ -187,6 +201,8 @@ def main():
                    "elements": wl.mesh.n_elems, "N": N, "dof": wl.dof, "dt": dt},
         "pid_s": 1.0 / value,
     }
+    if args.copy_calib:
+        line["copy_kernel_GBs"] = copy_gbs
     if prof is not None:
         lift_b, rhs_b = algorithmic_bytes_per_dof(N, False)
         ms_rhs, n_rhs = prof["rhs"]

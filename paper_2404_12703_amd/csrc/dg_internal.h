@@ -45,6 +45,7 @@ struct View {
   double t, dt, rkA, rkB;       // stage time, step, LSERK coefficients
   int cur;          // trace buffer read this stage (0: Utr0, 1: Utr1)
   int viscous, riemann, source, shock;
+  int remap;        // XCD-contiguous block order (single solve)
   real ind_a, ind_c, ind_s, alpha_min, alpha_max, ind_T; // indicator (ind_T precomputed threshold)
 };
 

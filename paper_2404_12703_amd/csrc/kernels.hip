@@ -49,14 +49,24 @@ __device__ __forceinline__ int lnode(int d, int l, int p, int q) {
 // which view and which element block this workgroup works on: a single
 // solve takes its view from the kernel arguments; a batch of solves looks its
 // request up in the block prefix sums and loads that request's view.
+// The hardware hands consecutive workgroups to the eight XCDs in turn; with
+// `remap` each XCD instead receives one contiguous range of element blocks, so
+// face neighbours (adjacent element indices) share that XCD's L2.  A bijection
+// of [0, gridDim.x).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, idx = b >> 3;
+  const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return start + idx;
+}
+
 template <bool BATCH, typename real>
 __device__ __forceinline__ View<real> select_view(const View<real> *views, const int *blk_start, int nreq,
                                                   const View<real> &single, int &lblk) {
-  const int b = blockIdx.x;
   if (!BATCH) {
-    lblk = b;
+    lblk = single.remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     return single;
   }
+  const int b = blockIdx.x;
   int r = 0;
   while (r + 1 < nreq && b >= blk_start[r + 1]) ++r;
   lblk = b - blk_start[r];

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -124,6 +125,10 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.riemann = p.riemann;
   v.source = p.source;
   v.shock = p.shock_capturing;
+  {
+    const char *env = std::getenv("DG_XCD_REMAP");
+    v.remap = env ? std::atoi(env) : 1;
+  }
   v.ind_a = (real)p.ind_a;
   v.ind_c = (real)p.ind_c;
   v.ind_s = (real)p.ind_s;
