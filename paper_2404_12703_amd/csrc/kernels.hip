@@ -37,6 +37,8 @@ struct Sz {
   static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, nf = 6 * n2;
   static constexpr int epb = (256 / n3) > 1 ? 256 / n3 : 1;  // elements per workgroup
   static constexpr int threads = ((epb * n3 + 63) / 64) * 64;
+  // waves per SIMD to plan registers for: two 512-thread workgroups per CU
+  static constexpr int minw = threads == 512 ? 4 : 1;
 };
 
 __device__ __forceinline__ int vnode(int n, int i, int j, int k) { return i + n * (j + n * k); }
@@ -199,7 +201,7 @@ __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *V
 // BR1 lifting: g = (1/J) [ sum_i D-hat (Ja^i_d v) + sum_faces v* (n shat)_d l-hat ]
 // ---------------------------------------------------------------------------
 template <int N, typename real, bool BATCH, bool SHOCK>
-__global__ void __launch_bounds__(Sz<N>::threads) k_lift(const View<real> *views, const int *blk_start, int nreq,
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_lift(const View<real> *views, const int *blk_start, int nreq,
                                                         View<real> single) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
@@ -357,7 +359,7 @@ __device__ __forceinline__ void prim2cons(const real *q, real gamma, real *U) {
 }
 
 template <int N, typename real, bool BATCH, bool SHOCK>
-__global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views, const int *blk_start, int nreq,
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<real> *views, const int *blk_start, int nreq,
                                                        View<real> single, int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
@@ -397,39 +399,9 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views,
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
 
-  real Ja[9];
-  real Fx[5], Fy[5], Fz[5];         // F_adv - F_visc (F_adv when SHOCK)
-  real Vx[5], Vy[5], Vz[5];         // F_visc (SHOCK only)
-  real P[6];
+  // FillFlux first: the face phase needs none of the volume data, so the
+  // volume fluxes are not held in registers across it
   if (active) {
-    real U[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
-    cons2prim(U, gam, Rg, P);
-    flux_adv<0>(U, P, Fx);
-    flux_adv<1>(U, P, Fy);
-    flux_adv<2>(U, P, Fz);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) Vx[c] = Vy[c] = Vz[c] = real(0);
-    if (visc) {
-      real g[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) g[c] = v.G[((int64_t)c * E + e) * n3 + a];
-      flux_visc<0>(P, g, mu, lam, Vx);
-      flux_visc<1>(P, g, mu, lam, Vy);
-      flux_visc<2>(P, g, mu, lam, Vz);
-      if constexpr (!SHOCK) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          Fx[c] -= Vx[c];
-          Fy[c] -= Vy[c];
-          Fz[c] -= Vz[c];
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) Ja[c] = v.Ja[((int64_t)c * E + e) * n3 + a];
-
     // FillFlux for the six faces of this element (surface nodes spread over the threads)
     for (int fn = a; fn < nf; fn += n3) {
       const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
@@ -486,6 +458,40 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_rhs(const View<real> *views,
 #pragma unroll
       for (int s = 0; s < 5; ++s) sS[le][s][fn] = primary ? Fs[s] * sh : -(Fs[s] * sh);
     }
+  }
+
+  real Ja[9];
+  real Fx[5], Fy[5], Fz[5];         // F_adv - F_visc (F_adv when SHOCK)
+  real Vx[5], Vy[5], Vz[5];         // F_visc (SHOCK only)
+  real P[6];
+  if (active) {
+    real U[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
+    cons2prim(U, gam, Rg, P);
+    flux_adv<0>(U, P, Fx);
+    flux_adv<1>(U, P, Fy);
+    flux_adv<2>(U, P, Fz);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Vx[c] = Vy[c] = Vz[c] = real(0);
+    if (visc) {
+      real g[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) g[c] = v.G[((int64_t)c * E + e) * n3 + a];
+      flux_visc<0>(P, g, mu, lam, Vx);
+      flux_visc<1>(P, g, mu, lam, Vy);
+      flux_visc<2>(P, g, mu, lam, Vz);
+      if constexpr (!SHOCK) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          Fx[c] -= Vx[c];
+          Fy[c] -= Vy[c];
+          Fz[c] -= Vz[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Ja[c] = v.Ja[((int64_t)c * E + e) * n3 + a];
   }
 
   real al = real(0);

@@ -127,7 +127,7 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.shock = p.shock_capturing;
   {
     const char *env = std::getenv("DG_XCD_REMAP");
-    v.remap = env ? std::atoi(env) : 1;
+    v.remap = env ? std::atoi(env) : 0;
   }
   v.ind_a = (real)p.ind_a;
   v.ind_c = (real)p.ind_c;
