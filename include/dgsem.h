@@ -68,7 +68,7 @@ typedef struct dg_params {
   int32_t precision;       /* 0 FP64; 1 mixed: FP32 fluxes and contractions, FP64 state, RK, setup */
   int32_t viscous;         /* 0 Euler, 1 Navier-Stokes with BR1 lifting                */
   int32_t source;          /* 0 none, 1 manufactured-solution source of Sec. 5.1 (see below) */
-  int32_t shock_capturing; /* 1: per-element DG/FV blend with the modal indicator     */
+  int32_t shock_capturing; /* 1: per-element DG/FV blend with the modal indicator (2 <= N <= 7) */
   int32_t check_finite;    /* 1: dg_advance verifies the state is finite at its end   */
   int32_t reserved;
   double gamma, R, Pr, mu;

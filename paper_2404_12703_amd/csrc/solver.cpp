@@ -46,8 +46,8 @@ dg_status check_params(const dg_params *p) {
   if (p->nodes != 0 && p->nodes != 1) return fail(DG_EINVAL, "nodes must be 0 (Gauss) or 1 (Lobatto)");
   if (p->riemann != 0 && p->riemann != 1) return fail(DG_EINVAL, "riemann must be 0 (LLF) or 1 (Roe)");
   if (p->precision != 0 && p->precision != 1) return fail(DG_EINVAL, "precision must be 0 or 1");
-  if (p->shock_capturing && (p->nodes != 1 || p->N < 2))
-    return fail(DG_EINVAL, "shock capturing needs Gauss-Lobatto nodes and N >= 2");
+  if (p->shock_capturing && (p->nodes != 1 || p->N < 2 || p->N > 7))
+    return fail(DG_EINVAL, "shock capturing needs Gauss-Lobatto nodes and 2 <= N <= 7");
   if (!(p->gamma > 1.0) || !(p->R > 0.0) || !(p->Pr > 0.0) || !(p->mu >= 0.0))
     return fail(DG_EINVAL, "need gamma > 1, R > 0, Pr > 0, mu >= 0");
   if (p->shock_capturing && !(p->alpha_max >= 0.0 && p->alpha_max <= 1.0 && p->alpha_min >= 0.0 && p->ind_a > 0.0))
