@@ -85,7 +85,7 @@ typedef struct dg_params {
  * (a,b) = bit0 ? (q,p) : (p,q);  p' = bit1 ? N-a : a;  q' = bit2 ? N-b : b.
  * Periodic meshes list the periodic partner as the neighbour. */
 typedef struct dg_mesh {
-  int64_t n_elems;
+  int64_t n_elems;           /* >= 1, with n_elems (N+1)^3 < 2^31 and 6 n_elems (N+1)^2 < 2^31 */
   int32_t n_geo;             /* 1 <= n_geo <= N                                       */
   int32_t reserved;
   const double *x_geo;       /* host [n_elems][3][(n_geo+1)^3], i fastest             */
@@ -101,7 +101,8 @@ int32_t dg_abi_version(void);
 
 /* Bytes of device workspace one solver needs (Sec. 4.3 reports the paper's
  * memory per DOF; this is ours).  Sizes all state, metric, trace and scratch
- * arrays for n_elems elements.  DG_EINVAL on bad parameters. */
+ * arrays for n_elems elements.  DG_EINVAL on bad parameters or an n_elems
+ * outside the range dg_mesh states. */
 dg_status dg_workspace_bytes(const dg_params *p, int64_t n_elems, size_t *bytes);
 
 /* Set up a solver: nodes and weights, D-hat and l-hat (Sec. 2.2 Eq. dgsem),

@@ -34,13 +34,16 @@ struct View {
   real *Utr1;       // [5][E*6][n2] conservative traces, pong
   real *Gtr;        // [12][E*6][n2] lifted-gradient traces
   real *G;          // [12][E][n3]  lifted gradients
+  // split viscous path (no shock capturing); these alias Gtr and G
+  real *Hv;         // [4][E*6][n2] own-side viscous normal flux F_v(prim, g).n of the face flux (momentum, energy)
+  real *Vol;        // [5][E][n3]  volume integral sum_i D-hat (Ja^i . (F_adv - F_v))
   const int2 *conn; // [E][6]: x = 6*nbr_elem + nbr_face, y = orient | primary << 3
   const double *Xs; // [3][E][n3] node positions (manufactured source only)
   const real *basis; // operator block, see BasisOffsets
   real *alpha;      // [E] blending factors
   real *alpha_raw;  // [E] indicator values before neighbour propagation
   const real *alpha_in; // [E] frozen blending factors or null
-  real gamma, Rgas, mu, lambda; // perfect gas, constant viscosity and conductivity
+  real gamma, Rgas, rRgas, mu, lambda; // perfect gas (rRgas = 1/R), constant viscosity and conductivity
   double Pr;        // Prandtl number (time-step estimate only)
   double t, dt, rkA, rkB;       // stage time, step, LSERK coefficients
   int cur;          // trace buffer read this stage (0: Utr0, 1: Utr1)

@@ -48,6 +48,22 @@ __device__ __forceinline__ int lnode(int d, int l, int p, int q) {
   return d == 0 ? l + n * (p + n * q) : (d == 1 ? p + n * (l + n * q) : p + n * (q + n * l));
 }
 
+// Buffers that are read along face lines hold the volume nodes with padded
+// strides: row (fixed j, k) n + 1 values, plane (fixed k) n (n + 1).  A wave
+// prolongs one face; unpadded, the lanes of a xi face read n apart, which for
+// n = 8 puts eight distinct doubles on each LDS bank pair.
+template <int n>
+struct Pad {
+  static constexpr int row = n + 1, plane = n * (n + 1), size = n * n * (n + 1);
+  static __device__ __forceinline__ int at(int i, int j, int k) { return i + row * j + plane * k; }
+  // the line normal to face f through face node pq, in padded coordinates
+  static __device__ __forceinline__ void face_line(int f, int pq, int &base, int &stride) {
+    const int d = f >> 1, p = pq % n, q = pq / n;
+    base = d == 0 ? row * p + plane * q : (d == 1 ? p + plane * q : p + row * q);
+    stride = d == 0 ? 1 : (d == 1 ? row : plane);
+  }
+};
+
 // which view and which element block this workgroup works on: a single
 // solve takes its view from the kernel arguments; a batch of solves looks its
 // request up in the block prefix sums and loads that request's view.
@@ -217,7 +233,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_lift(const View
   const bool active = le < epb && e < v.E;
   const int64_t E = v.E;
   const int64_t Ef = E * 6 * n2;  // stride of one variable in the face arrays
-  const real gam = v.gamma, Rg = v.Rgas;
+  const real gam = v.gamma, rR = v.rRgas;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
   real P[6];
@@ -225,7 +241,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_lift(const View
     real U[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
-    cons2prim(U, gam, Rg, P);
+    cons2prim(U, gam, rR, P);
   }
   if constexpr (SHOCK) {
     // indicator value of this element (neighbour propagation follows in k_rhs)
@@ -257,8 +273,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_lift(const View
         Uo[s] = tr[s * Ef + io];
         Un[s] = tr[s * Ef + in];
       }
-      cons2prim(Uo, gam, Rg, Po);
-      cons2prim(Un, gam, Rg, Pn);
+      cons2prim(Uo, gam, rR, Po);
+      cons2prim(Un, gam, rR, Pn);
       const real vo[4] = {Po[1], Po[2], Po[3], Po[5]}, vn[4] = {Pn[1], Pn[2], Pn[3], Pn[5]};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -394,7 +410,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
   const bool active = le < epb && e < v.E;
   const int64_t E = v.E;
   const int64_t Ef = E * 6 * n2;
-  const real gam = v.gamma, Rg = v.Rgas, mu = v.mu, lam = v.lambda;
+  const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
   const bool visc = v.viscous != 0;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
@@ -417,8 +433,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         Um[s] = tr[s * Ef + im];
         Us[s] = tr[s * Ef + is];
       }
-      cons2prim(Um, gam, Rg, Pm);
-      cons2prim(Us, gam, Rg, Ps);
+      cons2prim(Um, gam, rR, Pm);
+      cons2prim(Us, gam, rR, Ps);
       real nsv[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) nsv[d] = primary ? v.NS[d * Ef + io] : -v.NS[d * Ef + io];
@@ -468,7 +484,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
     real U[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
-    cons2prim(U, gam, Rg, P);
+    cons2prim(U, gam, rR, P);
     flux_adv<0>(U, P, Fx);
     flux_adv<1>(U, P, Fy);
     flux_adv<2>(U, P, Fz);
@@ -582,8 +598,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
           real UL[5], UR[5], PL[6], PR[6], F[5];
           prim2cons(qL, gam, UL);
           prim2cons(qR, gam, UR);
-          cons2prim(UL, gam, Rg, PL);
-          cons2prim(UR, gam, Rg, PR);
+          cons2prim(UL, gam, rR, PL);
+          cons2prim(UR, gam, rR, PR);
           riemann_llf(UL, PL, UR, PR, nv, gam, F);
 #pragma unroll
           for (int c = 0; c < 5; ++c) sB[le][11 + c][a] = F[c] * sh;
@@ -715,6 +731,374 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
 }
 
 // ---------------------------------------------------------------------------
+// Viscous operator without shock capturing, in two sweeps that exchange as
+// little as possible through HBM:
+//   k_volume : the BR1 lifting of k_lift with g kept on chip.  From the
+//              lifted gradient it forms (a) at each own face node this side's
+//              viscous normal flux H = F_v(prim, g) . n, with n in the primary
+//              side's orientation, and (b) at the volume nodes the complete
+//              volume integral of F_adv - F_v (VolInt).  Writes H (4 values
+//              per face node: the mass component is zero) and the volume
+//              integral (5 per node).
+//   k_surface: FillFlux from both sides' U traces and both sides' H (the
+//              BR1 viscous face flux is the mean of the two H), the SurfInt
+//              gather, ApplyJac, the stage update and the next U traces.
+// Both sweeps evaluate the same expressions in the same order as k_lift +
+// k_rhs.  Between the sweeps 5 volume and 4 face values per node cross HBM
+// instead of 12 and 12, and the metrics are read once per stage.
+// ---------------------------------------------------------------------------
+template <int N>
+struct VolLds {
+  using S = Sz<N>;
+  static constexpr int n3 = S::n3, nf = S::nf;
+  // per-element offsets.  Lifting: primitives u, v, w, T (4 rows of n3), the
+  // nine metric rows Ja^i_d (9 x n3), BR1 face averages (4 x nf) and own
+  // outward n shat (3 x nf).  g (12 padded rows) then covers the first three
+  // blocks, and the 15 rows of contravariant fluxes the whole area.
+  static constexpr int V = 0, J = 4 * n3, Avg = 13 * n3, Ns = Avg + 4 * nf, G = 0, F = 0;
+  static constexpr int gsz = Pad<S::n>::size;  // one padded row of g
+  static constexpr int rows = (Ns + 3 * nf) > 15 * n3 ? (Ns + 3 * nf) : 15 * n3;
+  static constexpr int fpt = (nf + n3 - 1) / n3;  // face nodes per thread
+  static_assert(12 * gsz <= Ns, "g must not cover n shat");
+};
+
+template <int N, typename real, bool BATCH>
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const View<real> *views, const int *blk_start,
+                                                                         int nreq, View<real> single) {
+  using S = Sz<N>;
+  using L = VolLds<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
+  int lblk;
+  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
+  __shared__ Smem<N, real> sb;
+  __shared__ real sA[epb][L::rows];
+  load_basis<N, real>(sb, v.basis);
+  const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
+  const int64_t e = (int64_t)lblk * epb + le;
+  const bool active = le < epb && e < v.E;
+  real *const sm = sA[le < epb ? le : 0];
+  // row strides of the volume and face arrays; per-lane indices are 32-bit
+  // (the host keeps every row below 2^31 entries)
+  const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
+  const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
+  const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
+  const real *tr = v.cur ? v.Utr1 : v.Utr0;
+  const int i = a % n, j = (a / n) % n, k = a / n2;
+  real U[5];
+  real pf[L::fpt][3];  // own face velocity at this thread's face nodes
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) U[c] = (real)(v.U + c * Ev)[vi];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + a] = (v.Ja + c * Ev)[vi];
+    real P[6];
+    cons2prim(U, gam, rR, P);
+    sm[L::V + 0 * n3 + a] = P[1];
+    sm[L::V + 1 * n3 + a] = P[2];
+    sm[L::V + 2 * n3 + a] = P[3];
+    sm[L::V + 3 * n3 + a] = P[5];
+    // Lift_FillFlux: the BR1 average of both sides' traces, and this side's
+    // outward n shat and face velocity for its viscous flux later on
+#pragma unroll
+    for (int r = 0; r < L::fpt; ++r) {
+      const int fn = a + r * n3;
+      if (fn < nf) {
+        const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
+        const int2 c = v.conn[e * 6 + f];
+        int pp, qq;
+        orient_map(c.y & 7, p, q, N, pp, qq);
+        const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
+        real Uo[5], Un[5], Po[6], Pn[6];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+          Uo[s] = (tr + s * Ef)[io];
+          Un[s] = (tr + s * Ef)[in];
+        }
+        cons2prim(Uo, gam, rR, Po);
+        cons2prim(Un, gam, rR, Pn);
+        const real vo[4] = {Po[1], Po[2], Po[3], Po[5]}, vn[4] = {Pn[1], Pn[2], Pn[3], Pn[5]};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) sm[L::Avg + s * nf + fn] = real(0.5) * (vo[s] + vn[s]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          sm[L::Ns + d * nf + fn] = (v.NS + d * Ef)[io];
+          pf[r][d] = Po[1 + d];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  real Fc[15];  // contravariant fluxes Ja^i . (F_adv - F_v), i = 0..2
+  real g[12];
+  if (active) {
+    // Lift_VolInt along the three computational directions
+    real JG[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) JG[c] = real(0);
+#pragma unroll
+    for (int ci = 0; ci < 3; ++ci) {
+      const int idx = ci == 0 ? i : (ci == 1 ? j : k);
+      const real *Jr = sm + L::J + 3 * ci * n3;
+#pragma unroll
+      for (int al = 0; al < n; ++al) {
+        const int src = ci == 0 ? vnode(n, al, j, k) : (ci == 1 ? vnode(n, i, al, k) : vnode(n, i, j, al));
+        const real dh = sb.Dh[idx * n + al];
+        // D-hat times the metric first: 3 products and 12 multiply-adds per source node
+        const real dj[3] = {dh * Jr[src], dh * Jr[n3 + src], dh * Jr[2 * n3 + src]};
+        const real vv[4] = {sm[L::V + src], sm[L::V + n3 + src], sm[L::V + 2 * n3 + src], sm[L::V + 3 * n3 + src]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) JG[d * 4 + s] += dj[d] * vv[s];
+      }
+    }
+    // Lift_SurfInt: the face average times n shat, through l-hat
+    const int pqf[3] = {j + n * k, i + n * k, i + n * j};
+    const int lf[3] = {i, j, k};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      const real lh = (f & 1) ? sb.lhp[lf[d]] : sb.lhm[lf[d]];
+      const int fn = f * n2 + pqf[d];
+      const real av[4] = {sm[L::Avg + fn], sm[L::Avg + nf + fn], sm[L::Avg + 2 * nf + fn], sm[L::Avg + 3 * nf + fn]};
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) {
+        const real nl = sm[L::Ns + dd * nf + fn] * lh;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) JG[dd * 4 + s] += av[s] * nl;
+      }
+    }
+    const real iJ = v.invJ[vi];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) g[c] = JG[c] * iJ;
+    // volume fluxes at this node, projected on the three contravariant directions
+    real P[6];
+    cons2prim(U, gam, rR, P);
+    real Fx[5], Fy[5], Fz[5], Vx[5], Vy[5], Vz[5];
+    flux_adv<0>(U, P, Fx);
+    flux_adv<1>(U, P, Fy);
+    flux_adv<2>(U, P, Fz);
+    flux_visc<0>(P, g, mu, lam, Vx);
+    flux_visc<1>(P, g, mu, lam, Vy);
+    flux_visc<2>(P, g, mu, lam, Vz);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      Fx[c] -= Vx[c];
+      Fy[c] -= Vy[c];
+      Fz[c] -= Vz[c];
+    }
+#pragma unroll
+    for (int ci = 0; ci < 3; ++ci) {
+      const real j0 = sm[L::J + (3 * ci) * n3 + a], j1 = sm[L::J + (3 * ci + 1) * n3 + a],
+                 j2 = sm[L::J + (3 * ci + 2) * n3 + a];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Fc[5 * ci + c] = j0 * Fx[c] + j1 * Fy[c] + j2 * Fz[c];
+    }
+  }
+  __syncthreads();  // the rows read above are covered by g below
+  if (active) {
+    const int pa = Pad<n>::at(i, j, k);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sm[L::G + c * L::gsz + pa] = g[c];
+  }
+  __syncthreads();
+  if (active) {
+    // Lift_ProlongToFace of g, then this side's viscous normal flux
+#pragma unroll
+    for (int r = 0; r < L::fpt; ++r) {
+      const int fn = a + r * n3;
+      if (fn < nf) {
+        const int f = fn / n2, pq = fn - f * n2;
+        int base, stride;
+        Pad<n>::face_line(f, pq, base, stride);
+        const real *lv = (f & 1) ? sb.lp : sb.lm;
+        real gt[12];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) gt[s] = real(0);
+#pragma unroll
+        for (int l = 0; l < n; ++l) {
+          const real lw = lv[l];
+          const real *row = sm + L::G + base + l * stride;
+#pragma unroll
+          for (int s = 0; s < 12; ++s) gt[s] += lw * row[s * L::gsz];
+        }
+        const bool primary = (v.conn[e * 6 + f].y >> 3) & 1;
+        real nsv[3];
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+          const real ns = sm[L::Ns + dd * nf + fn];
+          nsv[dd] = primary ? ns : -ns;
+        }
+        const real ish = real(1) / sqrt(nsv[0] * nsv[0] + nsv[1] * nsv[1] + nsv[2] * nsv[2]);
+        const real nv[3] = {nsv[0] * ish, nsv[1] * ish, nsv[2] * ish};
+        const real Pf[6] = {real(0), pf[r][0], pf[r][1], pf[r][2], real(0), real(0)};
+        real H[5] = {0, 0, 0, 0, 0}, tmp[5];
+        flux_visc<0>(Pf, gt, mu, lam, tmp);
+#pragma unroll
+        for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[0];
+        flux_visc<1>(Pf, gt, mu, lam, tmp);
+#pragma unroll
+        for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[1];
+        flux_visc<2>(Pf, gt, mu, lam, tmp);
+#pragma unroll
+        for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[2];
+#pragma unroll
+        for (int s = 1; s < 5; ++s) (v.Hv + (s - 1) * Ef)[fb + fn] = H[s];
+      }
+    }
+  }
+  __syncthreads();  // g and n shat are read above; the flux rows below cover them
+  // VolInt: all three directions' fluxes at once
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < 15; ++c) sm[L::F + c * n3 + a] = Fc[c];
+  }
+  __syncthreads();
+  if (active) {
+    real Vi[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int ci = 0; ci < 3; ++ci) {
+      const int idx = ci == 0 ? i : (ci == 1 ? j : k);
+#pragma unroll
+      for (int alp = 0; alp < n; ++alp) {
+        const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
+        const real dh = sb.Dh[idx * n + alp];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Vi[c] += dh * sm[L::F + (5 * ci + c) * n3 + src];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) (v.Vol + c * Ev)[vi] = Vi[c];
+  }
+}
+
+template <int N, typename real, bool BATCH>
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
+                                                                          int nreq, View<real> single, int mode) {
+  using S = Sz<N>;
+  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
+  int lblk;
+  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
+  __shared__ Smem<N, real> sb;
+  __shared__ real sB[epb][5][Pad<n>::size];
+  __shared__ real sS[epb][5][nf];
+  load_basis<N, real>(sb, v.basis);
+  const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
+  const int64_t e = (int64_t)lblk * epb + le;
+  const bool active = le < epb && e < v.E;
+  const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
+  const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
+  const real gam = v.gamma, rR = v.rRgas;
+  const real *tr = v.cur ? v.Utr1 : v.Utr0;
+  const int i = a % n, j = (a / n) % n, k = a / n2;
+  if (active) {
+    // FillFlux: Riemann flux of the U traces minus the mean of both sides' H
+    for (int fn = a; fn < nf; fn += n3) {
+      const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
+      const int2 c = v.conn[e * 6 + f];
+      const bool primary = (c.y >> 3) & 1;
+      int pp, qq;
+      orient_map(c.y & 7, p, q, N, pp, qq);
+      const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
+      const uint32_t im = primary ? io : in, is = primary ? in : io;
+      real Um[5], Us[5], Pm[6], Ps[6];
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        Um[s] = (tr + s * Ef)[im];
+        Us[s] = (tr + s * Ef)[is];
+      }
+      cons2prim(Um, gam, rR, Pm);
+      cons2prim(Us, gam, rR, Ps);
+      real nsv[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const real ns = (v.NS + d * Ef)[io];
+        nsv[d] = primary ? ns : -ns;
+      }
+      const real sh = sqrt(nsv[0] * nsv[0] + nsv[1] * nsv[1] + nsv[2] * nsv[2]);
+      const real nv[3] = {nsv[0] / sh, nsv[1] / sh, nsv[2] / sh};
+      real Fs[5];
+      if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs);
+      else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs);
+#pragma unroll
+      for (int s = 1; s < 5; ++s) Fs[s] -= real(0.5) * ((v.Hv + (s - 1) * Ef)[im] + (v.Hv + (s - 1) * Ef)[is]);
+#pragma unroll
+      for (int s = 0; s < 5; ++s) sS[le][s][fn] = primary ? Fs[s] * sh : -(Fs[s] * sh);
+    }
+  }
+  __syncthreads();
+  double Unew[5] = {0, 0, 0, 0, 0};
+  if (active) {
+    real V[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) V[c] = (v.Vol + c * Ev)[vi];
+    // SurfInt gather (one writer per entry) and ApplyJac
+    const int pqf[3] = {j + n * k, i + n * k, i + n * j};
+    const int lf[3] = {i, j, k};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      const real lh = (f & 1) ? sb.lhp[lf[d]] : sb.lhm[lf[d]];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) V[c] += sS[le][c][f * n2 + pqf[d]] * lh;
+    }
+    const real iJ = v.invJ[vi];
+    double R[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) R[c] = (double)(-(V[c] * iJ));
+    if (v.source == 1) {
+      const double x = v.Xs[vi], y = (v.Xs + Ev)[vi], z = (v.Xs + 2 * Ev)[vi];
+      const double cs = 0.1 * M_PI * cos(M_PI * (x + y + z - v.t));
+      const double gg = (double)gam;
+      R[0] += 2.0 * cs;
+      R[1] += 3.0 * cs;
+      R[2] += 3.0 * cs;
+      R[3] += 3.0 * cs;
+      R[4] += 2.0 * (3.0 * gg - 2.0) / (gg - 1.0) * cs;
+    }
+    if (mode == 1) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) (v.R + c * Ev)[vi] = R[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double *dUc = v.dU + c * Ev, *Uc = v.U + c * Ev;
+        const double du = v.rkA * dUc[vi] + v.dt * R[c];
+        dUc[vi] = du;
+        Unew[c] = Uc[vi] + v.rkB * du;
+        Uc[vi] = Unew[c];
+      }
+    }
+  }
+  if (mode == 0) {
+    // ProlongToFace of the updated state for the next stage
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sB[le][c][Pad<n>::at(i, j, k)] = (real)Unew[c];
+    }
+    __syncthreads();
+    if (active) {
+      real *trn = v.cur ? v.Utr0 : v.Utr1;
+      for (int fn = a; fn < nf; fn += n3) {
+        const int f = fn / n2, pq = fn - f * n2;
+        int base, stride;
+        Pad<n>::face_line(f, pq, base, stride);
+        const real *lv = (f & 1) ? sb.lp : sb.lm;
+        real s[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int l = 0; l < n; ++l) {
+          const real lw = lv[l];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) s[c] += lw * sB[le][c][base + l * stride];
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = s[c];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // reductions (per-block partials; the host finishes them)
 // ---------------------------------------------------------------------------
 template <int N, typename real>
@@ -730,7 +1114,7 @@ __global__ void __launch_bounds__(256) k_dt(View<real> v, double *out) {
     double U[5], P[6];
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = v.U[((int64_t)c * v.E + e) * n3 + a];
-    cons2prim(U, gam, (double)v.Rgas, P);
+    cons2prim(U, gam, (double)v.rRgas, P);
     const double c = sqrt(gam * P[4] / P[0]);
     const double iJ = (double)v.invJ[e * n3 + a];
     double lamsum = 0.0, vis = 0.0;
@@ -861,12 +1245,13 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
       else k_trace<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       break;
     case K_LIFT:
+      // shock capturing: indicator (+ lifting with g stored); viscous: the split volume sweep
       if (v0.shock) {
         if (batch) k_lift<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
         else k_lift<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       } else {
-        if (batch) k_lift<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-        else k_lift<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        if (batch) k_volume<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        else k_volume<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       }
       break;
     case K_RHS:
@@ -877,6 +1262,9 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
         } else {
           return hipErrorInvalidValue;
         }
+      } else if (v0.viscous) {
+        if (batch) k_surface<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        else k_surface<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       } else {
         if (batch) k_rhs<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
         else k_rhs<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);

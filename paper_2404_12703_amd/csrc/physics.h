@@ -8,18 +8,20 @@
 
 namespace dg {
 
-// prim = (rho, u, v, w, p, T) from U = (rho, rho u, rho v, rho w, rho e)
+// prim = (rho, u, v, w, p, T) from U = (rho, rho u, rho v, rho w, rho e);
+// rRgas = 1/R.  One reciprocal of rho replaces four divisions.
 template <typename real>
-__device__ __forceinline__ void cons2prim(const real *U, real gamma, real Rgas, real *P) {
+__device__ __forceinline__ void cons2prim(const real *U, real gamma, real rRgas, real *P) {
   const real rho = U[0];
-  const real u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
+  const real ir = real(1) / rho;
+  const real u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
   const real p = (gamma - real(1)) * (U[4] - real(0.5) * rho * (u * u + v * v + w * w));
   P[0] = rho;
   P[1] = u;
   P[2] = v;
   P[3] = w;
   P[4] = p;
-  P[5] = p / (rho * Rgas);
+  P[5] = p * (ir * rRgas);
 }
 
 // advective flux in Cartesian direction d (compile-time)

@@ -247,11 +247,12 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
 
 // one RK stage for every active request
 dg_status tick(dg_server *sv) {
-  std::map<std::tuple<int, int, int>, std::vector<Request *>> groups;
+  // one group per kernel set: degree, precision, shock capturing, viscosity
+  std::map<std::tuple<int, int, int, int>, std::vector<Request *>> groups;
   for (int64_t id : sv->active) {
     Request &r = *sv->reqs[id];
     if (r.retiring || r.step >= r.n_steps) continue;
-    groups[{r.p.N, r.p.precision, r.p.shock_capturing}].push_back(&r);
+    groups[{r.p.N, r.p.precision, r.p.shock_capturing, r.p.viscous}].push_back(&r);
   }
   for (auto &kv : groups) {
     const int N = std::get<0>(kv.first);
@@ -374,7 +375,7 @@ dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, 
   if (rc) return rc;
   if (!m || !m->x_geo || !m->nbr_elem || !m->nbr_face || !m->nbr_orient || !U0_host || !req_id)
     return fail(DG_EINVAL, "missing mesh, state or id pointer");
-  if (m->n_elems < 1 || m->n_elems * 6 >= INT32_MAX || m->n_geo < 1 || m->n_geo > p->N)
+  if (!elems_in_range(p->N, m->n_elems) || m->n_geo < 1 || m->n_geo > p->N)
     return fail(DG_EINVAL, "bad mesh sizes");
   if (n_steps < 0 || !std::isfinite(dt) || dt == 0.0) return fail(DG_EINVAL, "need n_steps >= 0 and dt != 0");
   std::unique_ptr<Request> r(new Request());

@@ -77,8 +77,11 @@ Layout make_layout(const dg_params &p, int64_t E) {
   L.NS = take(3 * E * 6 * n2 * rs);
   L.Utr0 = take(5 * E * 6 * n2 * rs);
   L.Utr1 = take(5 * E * 6 * n2 * rs);
-  L.Gtr = p.viscous ? take(12 * E * 6 * n2 * rs) : SIZE_MAX;
-  L.G = p.viscous ? take(12 * E * n3 * rs) : SIZE_MAX;
+  // shock capturing keeps g and its traces (12 rows each); the split viscous
+  // path stores one side's viscous face flux (4 rows) and the volume integral (5)
+  const int64_t gtr_rows = p.shock_capturing ? 12 : 4, g_rows = p.shock_capturing ? 12 : 5;
+  L.Gtr = p.viscous ? take(gtr_rows * E * 6 * n2 * rs) : SIZE_MAX;
+  L.G = p.viscous ? take(g_rows * E * n3 * rs) : SIZE_MAX;
   L.conn = take(6 * E * sizeof(int2));
   L.Xs = p.source ? take(3 * E * n3 * 8) : SIZE_MAX;
   L.basis = take(BasisOffsets(n).total * rs);
@@ -105,6 +108,8 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.Utr1 = (real *)at(L.Utr1);
   v.Gtr = (real *)at(L.Gtr);
   v.G = (real *)at(L.G);
+  v.Hv = v.Gtr;
+  v.Vol = v.G;
   v.conn = (const int2 *)at(L.conn);
   v.Xs = (const double *)at(L.Xs);
   v.basis = (const real *)at(L.basis);
@@ -113,6 +118,7 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.alpha_in = nullptr;
   v.gamma = (real)p.gamma;
   v.Rgas = (real)p.R;
+  v.rRgas = (real)(1.0 / p.R);
   v.mu = (real)p.mu;
   v.lambda = (real)(p.gamma * p.R * p.mu / ((p.gamma - 1.0) * p.Pr));
   v.Pr = p.Pr;
@@ -284,7 +290,7 @@ const char *dg_last_error(void) { return g_last_error.c_str(); }
 dg_status dg_workspace_bytes(const dg_params *p, int64_t n_elems, size_t *bytes) {
   dg_status rc = check_params(p);
   if (rc) return rc;
-  if (n_elems < 1 || n_elems * 6 >= INT32_MAX) return fail(DG_EINVAL, "n_elems out of range");
+  if (!elems_in_range(p->N, n_elems)) return fail(DG_EINVAL, "n_elems out of range");
   if (!bytes) return fail(DG_EINVAL, "bytes is NULL");
   *bytes = make_layout(*p, n_elems).total;
   return DG_OK;
@@ -298,7 +304,7 @@ dg_status dg_create(const dg_params *p, const dg_mesh *m, void *d_workspace, siz
   dg_status rc = check_params(p);
   if (rc) return rc;
   if (!m || !m->x_geo || !m->nbr_elem || !m->nbr_face || !m->nbr_orient) return fail(DG_EINVAL, "mesh arrays missing");
-  if (m->n_elems < 1 || m->n_elems * 6 >= INT32_MAX) return fail(DG_EINVAL, "n_elems out of range");
+  if (!elems_in_range(p->N, m->n_elems)) return fail(DG_EINVAL, "n_elems out of range");
   if (m->n_geo < 1 || m->n_geo > p->N) return fail(DG_EINVAL, "n_geo must be in 1..N");
   if (!d_workspace) return fail(DG_EINVAL, "workspace is NULL");
   if ((uintptr_t)d_workspace % 256) return fail(DG_EINVAL, "workspace must be 256-byte aligned");

@@ -19,6 +19,11 @@ struct Layout {
 
 Layout make_layout(const dg_params &p, int64_t E);
 dg_status check_params(const dg_params *p);
+// kernels index one row of a volume or face array with 32-bit lane offsets
+inline bool elems_in_range(int N, int64_t E) {
+  const int64_t n = N + 1;
+  return E >= 1 && E * n * n * n < INT32_MAX && E * 6 * n * n < INT32_MAX;
+}
 dg_status fail(dg_status code, const std::string &msg);
 
 extern const double RK_A[5], RK_B[5], RK_C[5];

@@ -42,12 +42,24 @@ def test_workspace_bytes_and_parameter_checks():
     p = W.params(7)
     nb = b.workspace_bytes(p, 13824)
     n3, n2, E = 512, 64, 13824
-    # state + RK register + metrics + normals + two U traces + g traces + g (FP64)
-    core = 8 * E * (5 * n3 + 5 * n3 + 9 * n3 + n3 + 3 * 6 * n2 + 2 * 5 * 6 * n2 + 12 * 6 * n2 + 12 * n3)
+    # state + RK register + metrics + normals + two U traces, then (viscous,
+    # no shock capturing) one side's viscous face flux (4 values per face
+    # node) and the volume integral (5 per node), all FP64
+    core = 8 * E * (5 * n3 + 5 * n3 + 9 * n3 + n3 + 3 * 6 * n2 + 2 * 5 * 6 * n2 + 4 * 6 * n2 + 5 * n3)
     assert core <= nb <= core * 1.01
     pm = dict(p)
     pm["precision"] = 1
     assert b.workspace_bytes(pm, E) < nb
+    # shock capturing keeps the lifted gradient and its traces (12 values each)
+    ps = W.params(7, node_type=1, shock=1)
+    ns = b.workspace_bytes(ps, E)
+    cs = 8 * E * (5 * n3 + 5 * n3 + 9 * n3 + n3 + 3 * 6 * n2 + 2 * 5 * 6 * n2 + 12 * 6 * n2 + 12 * n3)
+    assert cs <= ns <= cs * 1.01
+    # every row of a volume array must stay below 2^31 entries (32-bit lane offsets)
+    assert b.workspace_bytes(p, (2**31 - 1) // n3) > 0
+    with pytest.raises(b.DGError) as ei:
+        b.workspace_bytes(p, (2**31 - 1) // n3 + 1)
+    assert ei.value.code == b.DG_EINVAL
     for bad in (dict(N=0), dict(N=12), dict(gamma=1.0), dict(Pr=0.0), dict(mu=-1.0), dict(riemann=3),
                 dict(nodes=0, shock_capturing=1)):
         q = dict(p)
