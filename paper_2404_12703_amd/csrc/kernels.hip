@@ -94,7 +94,7 @@ __device__ __forceinline__ View<real> select_view(const View<real> *views, const
 template <int N, typename real>
 struct Smem {
   using S = Sz<N>;
-  real Dh[S::n * S::n];
+  real Dh[S::n * (S::n + 1)];  // rows padded to n + 1: lanes reading different rows hit different banks
   real lm[S::n], lp[S::n], lhm[S::n], lhp[S::n];
 };
 
@@ -103,7 +103,7 @@ __device__ __forceinline__ void load_basis(Smem<N, real> &sb, const real *basis)
   using S = Sz<N>;
   constexpr int n = S::n;
   BasisOffsets o(n);
-  for (int t = threadIdx.x; t < n * n; t += blockDim.x) sb.Dh[t] = basis[o.Dhat + t];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) sb.Dh[(t / n) * (n + 1) + t % n] = basis[o.Dhat + t];
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
     sb.lm[t] = basis[o.lm + t];
     sb.lp[t] = basis[o.lp + t];
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_lift(const View
 #pragma unroll
       for (int al = 0; al < n; ++al) {
         const int src = ci == 0 ? vnode(n, al, j, k) : (ci == 1 ? vnode(n, i, al, k) : vnode(n, i, j, al));
-        const real dh = sb.Dh[idx * n + al];
+        const real dh = sb.Dh[idx * (n + 1) + al];
         const real ja[3] = {sJ[le][0][src], sJ[le][1][src], sJ[le][2][src]};
         const real vv[4] = {sV[le][0][src], sV[le][1][src], sV[le][2][src], sV[le][3][src]};
 #pragma unroll
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
   __shared__ Smem<N, real> sb;
   __shared__ real sB[epb][ROWS][n3];
   __shared__ real sS[epb][5][nf];
-  __shared__ real sFV[SHOCK ? (2 * n * n + 3 * n + 1) : 1];  // D, Vinv, w, x, xhalf
+  __shared__ real sFV[SHOCK ? (n * n + 3 * n + 1) : 1];  // D, w, x, xhalf
   __shared__ real sAl[epb];
   __shared__ int sAny;
   load_basis<N, real>(sb, v.basis);
@@ -396,13 +396,12 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
     BasisOffsets o(n);
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
       sFV[t] = v.basis[o.D + t];
-      sFV[n * n + t] = v.basis[o.Vinv + t];
     }
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      sFV[2 * n * n + t] = v.basis[o.w + t];
-      sFV[2 * n * n + n + t] = v.basis[o.x + t];
+      sFV[n * n + t] = v.basis[o.w + t];
+      sFV[n * n + n + t] = v.basis[o.x + t];
     }
-    for (int t = threadIdx.x; t < n + 1; t += blockDim.x) sFV[2 * n * n + 2 * n + t] = v.basis[o.xhalf + t];
+    for (int t = threadIdx.x; t < n + 1; t += blockDim.x) sFV[n * n + 2 * n + t] = v.basis[o.xhalf + t];
     if (threadIdx.x == 0) sAny = 0;
   }
   const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
@@ -514,10 +513,9 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
   real Vfv[5] = {0, 0, 0, 0, 0};
   if constexpr (SHOCK) {
     const real *Dm = sFV;
-    const real *Vinv = sFV + n * n;
-    const real *wq = sFV + 2 * n * n;
-    const real *xq = sFV + 2 * n * n + n;
-    const real *xh = sFV + 2 * n * n + 2 * n;
+    const real *wq = sFV + n * n;
+    const real *xq = sFV + n * n + n;
+    const real *xh = sFV + n * n + 2 * n;
     __syncthreads();
     if (active && a == 0) {
       real a0;
@@ -649,7 +647,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
 #pragma unroll
       for (int alp = 0; alp < n; ++alp) {
         const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
-        const real dh = sb.Dh[idx * n + alp];
+        const real dh = sb.Dh[idx * (n + 1) + alp];
 #pragma unroll
         for (int c = 0; c < 5; ++c) V[c] += dh * sB[le][c][src];
         if (split) {
@@ -784,6 +782,17 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
+  // when a wave is one k-plane of one element (n^2 = 64), the k row of D-hat
+  // and the face of a face node are the same on every lane: scalar loads
+  // instead of LDS reads
+  constexpr bool plane_waves = n2 == 64 && epb == 1;
+  real dk[n];
+  if constexpr (plane_waves) {
+    const int ku = __builtin_amdgcn_readfirstlane(k);
+    const BasisOffsets o(n);
+#pragma unroll
+    for (int al = 0; al < n; ++al) dk[al] = v.basis[o.Dhat + ku * n + al];
+  }
   real U[5];
   real pf[L::fpt][3];  // own face velocity at this thread's face nodes
   if (active) {
@@ -803,7 +812,9 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     for (int r = 0; r < L::fpt; ++r) {
       const int fn = a + r * n3;
       if (fn < nf) {
-        const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
+        int f = fn / n2;
+        if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
+        const int pq = fn - f * n2, p = pq % n, q = pq / n;
         const int2 c = v.conn[e * 6 + f];
         int pp, qq;
         orient_map(c.y & 7, p, q, N, pp, qq);
@@ -842,7 +853,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
 #pragma unroll
       for (int al = 0; al < n; ++al) {
         const int src = ci == 0 ? vnode(n, al, j, k) : (ci == 1 ? vnode(n, i, al, k) : vnode(n, i, j, al));
-        const real dh = sb.Dh[idx * n + al];
+        const real dh = (plane_waves && ci == 2) ? dk[al] : sb.Dh[idx * (n + 1) + al];
         // D-hat times the metric first: 3 products and 12 multiply-adds per source node
         const real dj[3] = {dh * Jr[src], dh * Jr[n3 + src], dh * Jr[2 * n3 + src]};
         const real vv[4] = {sm[L::V + src], sm[L::V + n3 + src], sm[L::V + 2 * n3 + src], sm[L::V + 3 * n3 + src]};
@@ -908,7 +919,9 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     for (int r = 0; r < L::fpt; ++r) {
       const int fn = a + r * n3;
       if (fn < nf) {
-        const int f = fn / n2, pq = fn - f * n2;
+        int f = fn / n2;
+        if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
+        const int pq = fn - f * n2;
         int base, stride;
         Pad<n>::face_line(f, pq, base, stride);
         const real *lv = (f & 1) ? sb.lp : sb.lm;
@@ -948,7 +961,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     }
   }
   __syncthreads();  // g and n shat are read above; the flux rows below cover them
-  // VolInt: all three directions' fluxes at once
+  // VolInt: the fluxes of all three directions at once
   if (active) {
 #pragma unroll
     for (int c = 0; c < 15; ++c) sm[L::F + c * n3 + a] = Fc[c];
@@ -962,7 +975,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
 #pragma unroll
       for (int alp = 0; alp < n; ++alp) {
         const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
-        const real dh = sb.Dh[idx * n + alp];
+        const real dh = (plane_waves && ci == 2) ? dk[alp] : sb.Dh[idx * (n + 1) + alp];
 #pragma unroll
         for (int c = 0; c < 5; ++c) Vi[c] += dh * sm[L::F + (5 * ci + c) * n3 + src];
       }
@@ -991,10 +1004,13 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
   const real gam = v.gamma, rR = v.rRgas;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
+  constexpr bool plane_waves = n2 == 64 && epb == 1;  // a wave is one face of one element
   if (active) {
     // FillFlux: Riemann flux of the U traces minus the mean of both sides' H
     for (int fn = a; fn < nf; fn += n3) {
-      const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
+      int f = fn / n2;
+      if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
+      const int pq = fn - f * n2, p = pq % n, q = pq / n;
       const int2 c = v.conn[e * 6 + f];
       const bool primary = (c.y >> 3) & 1;
       int pp, qq;
@@ -1080,7 +1096,9 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
     if (active) {
       real *trn = v.cur ? v.Utr0 : v.Utr1;
       for (int fn = a; fn < nf; fn += n3) {
-        const int f = fn / n2, pq = fn - f * n2;
+        int f = fn / n2;
+        if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
+        const int pq = fn - f * n2;
         int base, stride;
         Pad<n>::face_line(f, pq, base, stride);
         const real *lv = (f & 1) ? sb.lp : sb.lm;
