@@ -64,6 +64,23 @@ struct Pad {
   }
 };
 
+// ProlongToFace of the five conservative variables at one face node from a
+// padded LDS copy of the element's state (rows of Pad<n>::size values).
+// Explicit multiply-adds in a fixed order: an element that recomputes its own
+// trace gets the bits its neighbours read from the stored one.
+template <int n, typename real>
+__device__ __forceinline__ void prolong_state(const real *rows, const real *lv, int base, int stride, real *out) {
+  real s[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int l = 0; l < n; ++l) {
+    const real lw = lv[l];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] = fma(lw, rows[c * Pad<n>::size + base + l * stride], s[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) out[c] = s[c];
+}
+
 // which view and which element block this workgroup works on: a single
 // solve takes its view from the kernel arguments; a batch of solves looks its
 // request up in the block prefix sums and loads that request's view.
@@ -123,29 +140,30 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *view
   int lblk;
   const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
-  __shared__ real sU[epb][5][n3];
+  __shared__ real sU[epb][5 * Pad<n>::size];
   load_basis<N, real>(sb, v.basis);
   const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
   const int64_t e = (int64_t)lblk * epb + le;
   const bool active = le < epb && e < v.E;
-  const int64_t E = v.E;
+  const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
+  const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
+  const int i = a % n, j = (a / n) % n, k = a / n2;
+  real *const su = sU[le < epb ? le : 0];
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sU[le][c][a] = (real)v.U[((int64_t)c * E + e) * n3 + a];
+    for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)(v.U + c * Ev)[vi];
   }
   __syncthreads();
   if (active) {
     real *tr = v.cur ? v.Utr1 : v.Utr0;
     for (int fn = a; fn < nf; fn += n3) {
-      const int f = fn / n2, pq = fn - f * n2, d = f >> 1, p = pq % n, q = pq / n;
-      const real *lv = (f & 1) ? sb.lp : sb.lm;
+      const int f = fn / n2, pq = fn - f * n2;
+      int base, stride;
+      Pad<n>::face_line(f, pq, base, stride);
+      real t[5];
+      prolong_state<n>(su, (f & 1) ? sb.lp : sb.lm, base, stride, t);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        real s = real(0);
-#pragma unroll
-        for (int l = 0; l < n; ++l) s += lv[l] * sU[le][c][lnode<n>(d, l, p, q)];
-        tr[((int64_t)c * E * 6 + e * 6) * n2 + fn] = s;
-      }
+      for (int c = 0; c < 5; ++c) (tr + c * Ef)[fb + fn] = t[c];
     }
   }
 }
@@ -1005,8 +1023,21 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
   constexpr bool plane_waves = n2 == 64 && epb == 1;  // a wave is one face of one element
+  real *const su = &sB[le < epb ? le : 0][0][0];
+  // the state, in registers for the update and in LDS for this element's own traces
+  double Uold[5] = {0, 0, 0, 0, 0};
   if (active) {
-    // FillFlux: Riemann flux of the U traces minus the mean of both sides' H
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      Uold[c] = (v.U + c * Ev)[vi];
+      su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Uold[c];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    // FillFlux: Riemann flux of the U traces minus the mean of both sides' H.
+    // This side's trace is recomputed from the state (the same bits as the
+    // stored one); the neighbour's is read.
     for (int fn = a; fn < nf; fn += n3) {
       int f = fn / n2;
       if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
@@ -1017,11 +1048,19 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
       orient_map(c.y & 7, p, q, N, pp, qq);
       const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
       const uint32_t im = primary ? io : in, is = primary ? in : io;
+      real Uo[5], Un[5];
+      {
+        int base, stride;
+        Pad<n>::face_line(f, pq, base, stride);
+        prolong_state<n>(su, (f & 1) ? sb.lp : sb.lm, base, stride, Uo);
+      }
+#pragma unroll
+      for (int s = 0; s < 5; ++s) Un[s] = (tr + s * Ef)[in];
       real Um[5], Us[5], Pm[6], Ps[6];
 #pragma unroll
       for (int s = 0; s < 5; ++s) {
-        Um[s] = (tr + s * Ef)[im];
-        Us[s] = (tr + s * Ef)[is];
+        Um[s] = primary ? Uo[s] : Un[s];
+        Us[s] = primary ? Un[s] : Uo[s];
       }
       cons2prim(Um, gam, rR, Pm);
       cons2prim(Us, gam, rR, Ps);
@@ -1078,19 +1117,20 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
     } else {
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        double *dUc = v.dU + c * Ev, *Uc = v.U + c * Ev;
+        double *dUc = v.dU + c * Ev;
         const double du = v.rkA * dUc[vi] + v.dt * R[c];
         dUc[vi] = du;
-        Unew[c] = Uc[vi] + v.rkB * du;
-        Uc[vi] = Unew[c];
+        Unew[c] = Uold[c] + v.rkB * du;
+        (v.U + c * Ev)[vi] = Unew[c];
       }
     }
   }
   if (mode == 0) {
     // ProlongToFace of the updated state for the next stage
+    // (every face-phase read of the old state is behind the barrier above)
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) sB[le][c][Pad<n>::at(i, j, k)] = (real)Unew[c];
+      for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Unew[c];
     }
     __syncthreads();
     if (active) {
@@ -1101,16 +1141,10 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
         const int pq = fn - f * n2;
         int base, stride;
         Pad<n>::face_line(f, pq, base, stride);
-        const real *lv = (f & 1) ? sb.lp : sb.lm;
-        real s[5] = {0, 0, 0, 0, 0};
+        real t[5];
+        prolong_state<n>(su, (f & 1) ? sb.lp : sb.lm, base, stride, t);
 #pragma unroll
-        for (int l = 0; l < n; ++l) {
-          const real lw = lv[l];
-#pragma unroll
-          for (int c = 0; c < 5; ++c) s[c] += lw * sB[le][c][base + l * stride];
-        }
-#pragma unroll
-        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = s[c];
+        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
       }
     }
   }
