@@ -93,11 +93,16 @@ def time_solver(P, wl, steps, warmup, profile_pass=True):
     return s, dt, el, prof
 
 
-def latency(P, wl, steps, repeats):
+def solve_latency(P, wl, steps, repeats, cfl=None, dt=None):
+    """`repeats` full solves (set_state from a device copy, `steps` RK steps,
+    state read back into device memory), each timed on the host clock.
+    Returns p50/p99 and the solver, holding the last solve's final state."""
     import torch
     s = P.Solver(wl.params, wl.mesh)
     s.set_state(wl.U0, 0.0)
-    dt = s.stable_dt(0.9, 0.9)
+    if dt is None:
+        c = wl.cfl if cfl is None else cfl
+        dt = s.stable_dt(c, c)
     U0 = torch.from_numpy(wl.U0).cuda()
     out = torch.empty_like(U0)
     lat = []
@@ -109,7 +114,10 @@ def latency(P, wl, steps, repeats):
         s.state_into(out)
         s.synchronize()
         lat.append(time.perf_counter() - t0)
-    return np.percentile(lat, 50), np.percentile(lat, 99)
+    st = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)), "repeats": repeats,
+          "steps": steps, "dt": dt, "solve": f"set_state + {steps} steps + get_state",
+          "value_at_p50": wl.dof * 5 * steps / float(np.percentile(lat, 50))}
+    return st, s, out
 
 
 def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30, max_active=64):
@@ -233,18 +241,35 @@ def main():
     del s
     torch.cuda.empty_cache()
     if not args.no_extras and not args.only_main:
-        # mixed precision: FP32 fluxes/contractions, FP64 state and RK, on the 32^3 mesh
-        wm = W.tgv_workload(K=32, N=7, steps=20, precision=1)
-        sm, dtm, elm, profm = time_solver(P, wm, 20, 2, profile_pass=False)
-        wd = W.tgv_workload(K=32, N=7, steps=20, precision=0)
-        sd, dtd, eld, _ = time_solver(P, wd, 20, 2, profile_pass=False)
-        line["mixed_tgv32"] = {"value_mixed": wm.dof * 5 * 20 / elm, "value_fp64": wd.dof * 5 * 20 / eld,
-                               "speedup": eld / elm, "steps": 20, "dof": wm.dof}
-        del sm, sd
+        # mixed precision against FP64 on the 32^3 mesh: 500 steps with the same dt,
+        # five full solves each; E_k and the state of the last solves compared
+        wd = W.tgv_workload(K=32, N=7, precision=0)
+        wm = W.tgv_workload(K=32, N=7, precision=1)
+        std, sd, Ud = solve_latency(P, wd, 500, 5)
+        stm, sm, Um = solve_latency(P, wm, 500, 5, dt=std["dt"])
+        Id, Im = sd.integrals(), sm.integrals()
+        line["mixed_tgv32"] = {
+            "dof": wd.dof, "steps": 500, "fp64": std, "mixed": stm,
+            "speedup": std["p50_s"] / stm["p50_s"],
+            "ek_rel_err": abs(Im[5] - Id[5]) / abs(Id[5]),
+            "state_rel_l2": float(torch.linalg.norm(Um - Ud) / torch.linalg.norm(Ud))}
+        del sd, sm, Ud, Um
         torch.cuda.empty_cache()
-        p50, p99 = latency(P, W.tgv_workload(K=args.K, N=7, steps=args.steps), args.steps, 5)
-        line["latency_s"] = {"p50": p50, "p99": p99, "solve": f"set_state + {args.steps} steps + get_state",
-                             "repeats": 5}
+        st, s2, _ = solve_latency(P, W.tgv_workload(K=args.K, N=7), args.steps, 20)
+        line["latency_tgv24"] = st
+        del s2
+        st, s1, _ = solve_latency(P, W.mms_workload(), 10, 20)
+        line["latency_mms"] = st
+        del s1
+        # the shock-capturing workload: 32^3 Lobatto N=5, indicator + FV blend
+        wb = W.blast_workload(K=32, N=5)
+        st, sbl, _ = solve_latency(P, wb, 200, 5)
+        sbl.set_state(wb.U0, 0.0)
+        sbl.rhs(0.0)
+        st["alpha_pos_fraction_t0"] = float(np.mean(sbl.alpha() > 0))
+        line["blast32"] = st
+        del sbl
+        torch.cuda.empty_cache()
         line["served"] = [served(P, W, args.serve_requests, 0, value, precision=pr) for pr in (0, 1)]
     if not args.no_cpu and not args.only_main:
         line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1))
