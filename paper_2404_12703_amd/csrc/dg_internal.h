@@ -32,9 +32,6 @@ struct View {
   const real *NS;   // [3][E*6][n2] outward n*shat of the face flux at this node
   real *Utr0;       // [5][E*6][n2] conservative traces, ping
   real *Utr1;       // [5][E*6][n2] conservative traces, pong
-  real *Gtr;        // [12][E*6][n2] lifted-gradient traces
-  real *G;          // [12][E][n3]  lifted gradients
-  // split viscous path (no shock capturing); these alias Gtr and G
   real *Hv;         // [4][E*6][n2] own-side viscous normal flux F_v(prim, g).n of the face flux (momentum, energy)
   real *Vol;        // [5][E][n3]  volume integral sum_i D-hat (Ja^i . (F_adv - F_v))
   const int2 *conn; // [E][6]: x = 6*nbr_elem + nbr_face, y = orient | primary << 3

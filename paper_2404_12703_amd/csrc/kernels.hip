@@ -5,22 +5,23 @@
 //   ConsToPrim, ProlongToFace, FillFlux, VolInt, SurfInt, ApplyJac and the
 //   Lift_* copies of BR1 (Sec. 2.2 "Second-Order Equations").
 //
-// Design (per RK stage, two sweeps over the elements; BR1 needs every
+// Design: one workgroup slot per element, one thread per volume node.  Per
+// RK stage with viscosity or shock capturing, two sweeps (BR1 needs every
 // neighbour's lifted gradient before any viscous face flux can be formed):
-//   k_lift : one workgroup slot per element.  Primitives -> LDS; the BR1
-//            face average from own and neighbour U traces; the weak lifting
-//            volume contraction with D-hat along the three lines; the surface
-//            gather with l-hat; times 1/J.  Writes g and its face traces.
-//   k_rhs  : fluxes F_adv - F_visc in registers, contravariant projection one
-//            direction at a time into LDS, D-hat contraction (VolInt); the
-//            face fluxes of the six faces (Riemann + BR1 viscous average),
-//            each computed by both neighbours from the same operands in the
-//            same order so both hold the same bits and nothing is stored;
-//            the per-DOF SurfInt gather (one writer per entry, as the paper's
-//            GPU SurfInt); ApplyJac; the LSERK stage update; and the next
-//            stage's U traces from the updated state (ProlongToFace).
-// Traces are ping-ponged between stages because k_rhs reads the neighbours'
-// traces of the old state while writing those of the new one.
+//   k_volume : (shock capturing) the a-priori indicator value of the element;
+//              BR1 lifting with g kept on chip; each own face node's viscous
+//              normal flux; the whole volume integral.
+//   k_surface: (shock capturing) the blending factor from the neighbours'
+//              indicator values and, where it is positive, the FV subcell
+//              operator; the face fluxes (Riemann + BR1 viscous mean) of the
+//              six faces, computed by both neighbours from the same operands
+//              in the same order so both hold the same bits and nothing is
+//              stored; the per-DOF SurfInt gather (one writer per entry, as
+//              the paper's GPU SurfInt); ApplyJac; the LSERK stage update; and
+//              the next stage's U traces (ProlongToFace).
+// Euler without shock capturing takes one sweep, k_rhs.
+// Traces are ping-ponged between stages because the last sweep reads the
+// neighbours' traces of the old state while writing those of the new one.
 // Layouts are structure-of-arrays with one contiguous (N+1)^3 block per
 // element and variable, so every global access of a workgroup is contiguous.
 #include <hip/hip_runtime.h>
@@ -231,152 +232,7 @@ __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *V
   return alpha;
 }
 
-// ---------------------------------------------------------------------------
-// BR1 lifting: g = (1/J) [ sum_i D-hat (Ja^i_d v) + sum_faces v* (n shat)_d l-hat ]
-// ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH, bool SHOCK>
-__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_lift(const View<real> *views, const int *blk_start, int nreq,
-                                                        View<real> single) {
-  using S = Sz<N>;
-  constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
-  int lblk;
-  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
-  __shared__ Smem<N, real> sb;
-  __shared__ real sV[epb][4][n3];
-  __shared__ real sJ[epb][3][n3];
-  __shared__ real sL[epb][12][nf];
-  load_basis<N, real>(sb, v.basis);
-  const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
-  const int64_t e = (int64_t)lblk * epb + le;
-  const bool active = le < epb && e < v.E;
-  const int64_t E = v.E;
-  const int64_t Ef = E * 6 * n2;  // stride of one variable in the face arrays
-  const real gam = v.gamma, rR = v.rRgas;
-  const real *tr = v.cur ? v.Utr1 : v.Utr0;
-  const int i = a % n, j = (a / n) % n, k = a / n2;
-  real P[6];
-  if (active) {
-    real U[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
-    cons2prim(U, gam, rR, P);
-  }
-  if constexpr (SHOCK) {
-    // indicator value of this element (neighbour propagation follows in k_rhs)
-    __shared__ real sVinv[n * n];
-    BasisOffsets o(n);
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) sVinv[t] = v.basis[o.Vinv + t];
-    __syncthreads();
-    const real al = indicator_raw<N, real>(v, sVinv, sV[le][0], sV[le][1], sV[le][2], sJ[le][0], sJ[le][1], sJ[le][2],
-                                           active, a, active ? P[0] * P[4] : real(0));
-    if (active && a == 0) v.alpha_raw[e] = al;
-    __syncthreads();
-  }
-  if (!v.viscous) return;  // uniform over the grid: the indicator was all that was asked
-  if (active) {
-    sV[le][0][a] = P[1];
-    sV[le][1][a] = P[2];
-    sV[le][2][a] = P[3];
-    sV[le][3][a] = P[5];
-    // Lift_FillFlux: v* (n shat) with v* the average of both sides' traces
-    for (int fn = a; fn < nf; fn += n3) {
-      const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
-      const int2 c = v.conn[e * 6 + f];
-      int pp, qq;
-      orient_map(c.y & 7, p, q, N, pp, qq);
-      const int64_t io = (e * 6) * n2 + fn, in = (int64_t)c.x * n2 + pp + n * qq;
-      real Uo[5], Un[5], Po[6], Pn[6];
-#pragma unroll
-      for (int s = 0; s < 5; ++s) {
-        Uo[s] = tr[s * Ef + io];
-        Un[s] = tr[s * Ef + in];
-      }
-      cons2prim(Uo, gam, rR, Po);
-      cons2prim(Un, gam, rR, Pn);
-      const real vo[4] = {Po[1], Po[2], Po[3], Po[5]}, vn[4] = {Pn[1], Pn[2], Pn[3], Pn[5]};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const real nsd = v.NS[d * Ef + io];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) sL[le][d * 4 + s][fn] = real(0.5) * (vo[s] + vn[s]) * nsd;
-      }
-    }
-  }
-  real JG[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) JG[c] = real(0);
-#pragma unroll
-  for (int ci = 0; ci < 3; ++ci) {
-    if (active) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) sJ[le][d][a] = v.Ja[((int64_t)(3 * ci + d) * E + e) * n3 + a];
-    }
-    __syncthreads();
-    if (active) {
-      const int idx = ci == 0 ? i : (ci == 1 ? j : k);
-#pragma unroll
-      for (int al = 0; al < n; ++al) {
-        const int src = ci == 0 ? vnode(n, al, j, k) : (ci == 1 ? vnode(n, i, al, k) : vnode(n, i, j, al));
-        const real dh = sb.Dh[idx * (n + 1) + al];
-        const real ja[3] = {sJ[le][0][src], sJ[le][1][src], sJ[le][2][src]};
-        const real vv[4] = {sV[le][0][src], sV[le][1][src], sV[le][2][src], sV[le][3][src]};
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) JG[d * 4 + s] += dh * (ja[d] * vv[s]);
-      }
-    }
-    __syncthreads();
-  }
-  real g[12];
-  if (active) {
-    // Lift_SurfInt: gather the six faces through l-hat
-    const int pqf[3] = {j + n * k, i + n * k, i + n * j};
-    const int lf[3] = {i, j, k};
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      const int d = f >> 1;
-      const real lh = (f & 1) ? sb.lhp[lf[d]] : sb.lhm[lf[d]];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) JG[c] += sL[le][c][f * n2 + pqf[d]] * lh;
-    }
-    const real iJ = v.invJ[e * n3 + a];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      g[c] = JG[c] * iJ;
-      v.G[((int64_t)c * E + e) * n3 + a] = g[c];
-    }
-  }
-  // Lift_ProlongToFace in three passes of four components through LDS
-#pragma unroll
-  for (int pass = 0; pass < 3; ++pass) {
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) sV[le][s][a] = g[pass * 4 + s];
-    }
-    __syncthreads();
-    if (active) {
-      for (int fn = a; fn < nf; fn += n3) {
-        const int f = fn / n2, pq = fn - f * n2, d = f >> 1, p = pq % n, q = pq / n;
-        const real *lv = (f & 1) ? sb.lp : sb.lm;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          real acc = real(0);
-#pragma unroll
-          for (int l = 0; l < n; ++l) acc += lv[l] * sV[le][s][lnode<n>(d, l, p, q)];
-          v.Gtr[(int64_t)(pass * 4 + s) * Ef + (e * 6) * n2 + fn] = acc;
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Time derivative and stage update.  mode 0: du = A du + dt R, U += B du and
-// the next stage's traces; mode 1: write R only.  SHOCK adds the a-priori
-// indicator and the convex DG/FV-subcell blend of Sec. 2.3.
-// ---------------------------------------------------------------------------
+// reconstruction helpers of the FV subcells
 template <typename real>
 __device__ __forceinline__ real minmod2(real a, real b) {
   if (a * b <= real(0)) return real(0);
@@ -392,272 +248,91 @@ __device__ __forceinline__ void prim2cons(const real *q, real gamma, real *U) {
   U[4] = q[4] / (gamma - real(1)) + real(0.5) * q[0] * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
 }
 
-template <int N, typename real, bool BATCH, bool SHOCK>
-__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<real> *views, const int *blk_start, int nreq,
-                                                       View<real> single, int mode) {
+// ---------------------------------------------------------------------------
+// Euler without shock capturing: one sweep per stage.  FillFlux (Riemann
+// flux of both sides' stored U traces), VolInt of F_adv through LDS one
+// direction at a time, the SurfInt gather, ApplyJac, the stage update and the
+// next U traces.  mode 0: du = A du + dt R, U += B du; mode 1: write R only.
+// ---------------------------------------------------------------------------
+template <int N, typename real, bool BATCH>
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<real> *views, const int *blk_start,
+                                                                      int nreq, View<real> single, int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
-  // LDS rows of n3 values per element: 0-4 contravariant flux (advective part
-  // when blending), 5-9 viscous contravariant flux; the blend reuses 0-15 for
-  // the indicator and the subcell operator before the volume integral.
-  constexpr int ROWS = SHOCK ? 16 : 5;
   int lblk;
   const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
-  __shared__ real sB[epb][ROWS][n3];
+  // contravariant fluxes of one direction (rows of n3), later the updated
+  // state (padded rows) for the next traces
+  __shared__ real sB[epb][5 * Pad<n>::size];
   __shared__ real sS[epb][5][nf];
-  __shared__ real sFV[SHOCK ? (n * n + 3 * n + 1) : 1];  // D, w, x, xhalf
-  __shared__ real sAl[epb];
-  __shared__ int sAny;
   load_basis<N, real>(sb, v.basis);
-  if constexpr (SHOCK) {
-    BasisOffsets o(n);
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-      sFV[t] = v.basis[o.D + t];
-    }
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      sFV[n * n + t] = v.basis[o.w + t];
-      sFV[n * n + n + t] = v.basis[o.x + t];
-    }
-    for (int t = threadIdx.x; t < n + 1; t += blockDim.x) sFV[n * n + 2 * n + t] = v.basis[o.xhalf + t];
-    if (threadIdx.x == 0) sAny = 0;
-  }
   const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
   const int64_t e = (int64_t)lblk * epb + le;
   const bool active = le < epb && e < v.E;
-  const int64_t E = v.E;
-  const int64_t Ef = E * 6 * n2;
-  const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
-  const bool visc = v.viscous != 0;
+  real *const sm = sB[le < epb ? le : 0];
+  const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
+  const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
+  const real gam = v.gamma, rR = v.rRgas;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
-
-  // FillFlux first: the face phase needs none of the volume data, so the
-  // volume fluxes are not held in registers across it
   if (active) {
-    // FillFlux for the six faces of this element (surface nodes spread over the threads)
+    // FillFlux for the six faces of this element (face nodes spread over the threads)
     for (int fn = a; fn < nf; fn += n3) {
       const int f = fn / n2, pq = fn - f * n2, p = pq % n, q = pq / n;
       const int2 c = v.conn[e * 6 + f];
       const bool primary = (c.y >> 3) & 1;
       int pp, qq;
       orient_map(c.y & 7, p, q, N, pp, qq);
-      const int64_t io = (e * 6) * n2 + fn, in = (int64_t)c.x * n2 + pp + n * qq;
-      const int64_t im = primary ? io : in, is = primary ? in : io;
+      const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
+      const uint32_t im = primary ? io : in, is = primary ? in : io;
       real Um[5], Us[5], Pm[6], Ps[6];
 #pragma unroll
       for (int s = 0; s < 5; ++s) {
-        Um[s] = tr[s * Ef + im];
-        Us[s] = tr[s * Ef + is];
+        Um[s] = (tr + s * Ef)[im];
+        Us[s] = (tr + s * Ef)[is];
       }
       cons2prim(Um, gam, rR, Pm);
       cons2prim(Us, gam, rR, Ps);
       real nsv[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) nsv[d] = primary ? v.NS[d * Ef + io] : -v.NS[d * Ef + io];
+      for (int d = 0; d < 3; ++d) {
+        const real ns = (v.NS + d * Ef)[io];
+        nsv[d] = primary ? ns : -ns;
+      }
       const real sh = sqrt(nsv[0] * nsv[0] + nsv[1] * nsv[1] + nsv[2] * nsv[2]);
-      const real nv[3] = {nsv[0] / sh, nsv[1] / sh, nsv[2] / sh};
+      const real ish = real(1) / sh;
+      const real nv[3] = {nsv[0] * ish, nsv[1] * ish, nsv[2] * ish};
       real Fs[5];
       if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs);
       else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs);
-      if (visc) {
-        real gm[12], gs[12], Fm[5] = {0, 0, 0, 0, 0}, Fv[5] = {0, 0, 0, 0, 0}, tmp[5];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) {
-          gm[s] = v.Gtr[s * Ef + im];
-          gs[s] = v.Gtr[s * Ef + is];
-        }
-        flux_visc<0>(Pm, gm, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fm[s] += tmp[s] * nv[0];
-        flux_visc<1>(Pm, gm, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fm[s] += tmp[s] * nv[1];
-        flux_visc<2>(Pm, gm, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fm[s] += tmp[s] * nv[2];
-        flux_visc<0>(Ps, gs, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fv[s] += tmp[s] * nv[0];
-        flux_visc<1>(Ps, gs, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fv[s] += tmp[s] * nv[1];
-        flux_visc<2>(Ps, gs, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fv[s] += tmp[s] * nv[2];
-#pragma unroll
-        for (int s = 0; s < 5; ++s) Fs[s] -= real(0.5) * (Fm[s] + Fv[s]);
-      }
 #pragma unroll
       for (int s = 0; s < 5; ++s) sS[le][s][fn] = primary ? Fs[s] * sh : -(Fs[s] * sh);
     }
   }
-
-  real Ja[9];
-  real Fx[5], Fy[5], Fz[5];         // F_adv - F_visc (F_adv when SHOCK)
-  real Vx[5], Vy[5], Vz[5];         // F_visc (SHOCK only)
-  real P[6];
+  real Ja[9], Fx[5], Fy[5], Fz[5];
+  double Uold[5] = {0, 0, 0, 0, 0};
   if (active) {
-    real U[5];
+    real U[5], P[6];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) U[c] = (real)v.U[((int64_t)c * E + e) * n3 + a];
+    for (int c = 0; c < 5; ++c) {
+      Uold[c] = (v.U + c * Ev)[vi];
+      U[c] = (real)Uold[c];
+    }
     cons2prim(U, gam, rR, P);
     flux_adv<0>(U, P, Fx);
     flux_adv<1>(U, P, Fy);
     flux_adv<2>(U, P, Fz);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Vx[c] = Vy[c] = Vz[c] = real(0);
-    if (visc) {
-      real g[12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) g[c] = v.G[((int64_t)c * E + e) * n3 + a];
-      flux_visc<0>(P, g, mu, lam, Vx);
-      flux_visc<1>(P, g, mu, lam, Vy);
-      flux_visc<2>(P, g, mu, lam, Vz);
-      if constexpr (!SHOCK) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          Fx[c] -= Vx[c];
-          Fy[c] -= Vy[c];
-          Fz[c] -= Vz[c];
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) Ja[c] = v.Ja[((int64_t)c * E + e) * n3 + a];
+    for (int c = 0; c < 9; ++c) Ja[c] = (v.Ja + c * Ev)[vi];
   }
-
-  real al = real(0);
-  real Vfv[5] = {0, 0, 0, 0, 0};
-  if constexpr (SHOCK) {
-    const real *Dm = sFV;
-    const real *wq = sFV + n * n;
-    const real *xq = sFV + n * n + n;
-    const real *xh = sFV + n * n + 2 * n;
-    __syncthreads();
-    if (active && a == 0) {
-      real a0;
-      if (v.alpha_in) {
-        a0 = v.alpha_in[e];
-      } else {
-        // the element's indicator value, raised to half of its face neighbours'
-        a0 = v.alpha_raw[e];
-#pragma unroll
-        for (int f = 0; f < 6; ++f) a0 = fmax(a0, real(0.5) * v.alpha_raw[v.conn[e * 6 + f].x / 6]);
-        a0 = fmin(a0, v.alpha_max);
-      }
-      sAl[le] = a0;
-    }
-    __syncthreads();
-    if (active) {
-      al = sAl[le];
-      if (a == 0) v.alpha[e] = al;
-      if (al > real(0)) sAny = 1;  // benign: every writer stores 1
-    }
-    __syncthreads();
-    if (sAny) {
-      // FV subcell operator (Sec. 2.3): rows 0-4 primitives, 5-7 Ja^d,
-      // 8-10 w_l d(Ja^d)/dxi, 11-15 interface fluxes
-      if (active) {
-        sB[le][0][a] = P[0];
-        sB[le][1][a] = P[1];
-        sB[le][2][a] = P[2];
-        sB[le][3][a] = P[3];
-        sB[le][4][a] = P[4];
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int l = d == 0 ? i : (d == 1 ? j : k);
-        const int pp = d == 0 ? j : i, qq = d == 2 ? j : k;
-        if (active) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) sB[le][5 + c][a] = Ja[3 * d + c];
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            real s = real(0);
-#pragma unroll
-            for (int m = 0; m < n; ++m) s += Dm[l * n + m] * sB[le][5 + c][lnode<n>(d, m, pp, qq)];
-            sB[le][8 + c][a] = wq[l] * s;
-          }
-        }
-        __syncthreads();
-        if (active && l < N) {
-          real Jh[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            real acc = sB[le][5 + c][lnode<n>(d, 0, pp, qq)];
-            for (int m = 0; m <= l; ++m) acc += sB[le][8 + c][lnode<n>(d, m, pp, qq)];
-            Jh[c] = acc;
-          }
-          const real sh = sqrt(Jh[0] * Jh[0] + Jh[1] * Jh[1] + Jh[2] * Jh[2]);
-          const real nv[3] = {Jh[0] / sh, Jh[1] / sh, Jh[2] / sh};
-          real qL[5], qR[5];
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            const real q0 = sB[le][c][lnode<n>(d, l, pp, qq)];
-            const real q1 = sB[le][c][lnode<n>(d, l + 1, pp, qq)];
-            real s0 = real(0), s1 = real(0);
-            if (l >= 1) {
-              const real qm = sB[le][c][lnode<n>(d, l - 1, pp, qq)];
-              s0 = minmod2((q0 - qm) / (xq[l] - xq[l - 1]), (q1 - q0) / (xq[l + 1] - xq[l]));
-            }
-            if (l + 1 <= N - 1) {
-              const real q2 = sB[le][c][lnode<n>(d, l + 2, pp, qq)];
-              s1 = minmod2((q1 - q0) / (xq[l + 1] - xq[l]), (q2 - q1) / (xq[l + 2] - xq[l + 1]));
-            }
-            qL[c] = q0 + s0 * (xh[l + 1] - xq[l]);
-            qR[c] = q1 - s1 * (xq[l + 1] - xh[l + 1]);
-          }
-          real UL[5], UR[5], PL[6], PR[6], F[5];
-          prim2cons(qL, gam, UL);
-          prim2cons(qR, gam, UR);
-          cons2prim(UL, gam, rR, PL);
-          cons2prim(UR, gam, rR, PR);
-          riemann_llf(UL, PL, UR, PR, nv, gam, F);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) sB[le][11 + c][a] = F[c] * sh;
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            real r = real(0);
-            if (l < N) r += sB[le][11 + c][a];
-            if (l > 0) r -= sB[le][11 + c][lnode<n>(d, l - 1, pp, qq)];
-            Vfv[c] += r / wq[l];
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-
   // VolInt: one computational direction at a time through LDS
   real V[5] = {0, 0, 0, 0, 0};
-  real Vv[5] = {0, 0, 0, 0, 0};
-  const bool split = SHOCK && al > real(0);
 #pragma unroll
   for (int ci = 0; ci < 3; ++ci) {
     if (active) {
-      if constexpr (SHOCK) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          if (split) {
-            sB[le][c][a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
-            sB[le][5 + c][a] = Ja[3 * ci + 0] * Vx[c] + Ja[3 * ci + 1] * Vy[c] + Ja[3 * ci + 2] * Vz[c];
-          } else {
-            sB[le][c][a] = Ja[3 * ci + 0] * (Fx[c] - Vx[c]) + Ja[3 * ci + 1] * (Fy[c] - Vy[c]) +
-                           Ja[3 * ci + 2] * (Fz[c] - Vz[c]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-          sB[le][c][a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
-      }
+      for (int c = 0; c < 5; ++c) sm[c * n3 + a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
     }
     __syncthreads();
     if (active) {
@@ -667,23 +342,13 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
         const real dh = sb.Dh[idx * (n + 1) + alp];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) V[c] += dh * sB[le][c][src];
-        if (split) {
-#pragma unroll
-          for (int c = 0; c < 5; ++c) Vv[c] -= dh * sB[le][5 + c][src];
-        }
+        for (int c = 0; c < 5; ++c) V[c] += dh * sm[c * n3 + src];
       }
     }
     __syncthreads();
   }
-
   double Unew[5] = {0, 0, 0, 0, 0};
   if (active) {
-    if (split) {
-      // (1 - alpha) V_DG,adv + alpha V_FV + V_DG,visc
-#pragma unroll
-      for (int c = 0; c < 5; ++c) V[c] = (real(1) - al) * V[c] + al * Vfv[c] + Vv[c];
-    }
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -694,12 +359,12 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
 #pragma unroll
       for (int c = 0; c < 5; ++c) V[c] += sS[le][c][f * n2 + pqf[d]] * lh;
     }
-    const real iJ = v.invJ[e * n3 + a];
+    const real iJ = v.invJ[vi];
     double R[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) R[c] = (double)(-(V[c] * iJ));
     if (v.source == 1) {
-      const double x = v.Xs[(0 * E + e) * n3 + a], y = v.Xs[(1 * E + e) * n3 + a], z = v.Xs[(2 * E + e) * n3 + a];
+      const double x = v.Xs[vi], y = (v.Xs + Ev)[vi], z = (v.Xs + 2 * Ev)[vi];
       const double cs = 0.1 * M_PI * cos(M_PI * (x + y + z - v.t));
       const double gg = (double)gam;
       R[0] += 2.0 * cs;
@@ -710,59 +375,133 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
     }
     if (mode == 1) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) v.R[((int64_t)c * E + e) * n3 + a] = R[c];
+      for (int c = 0; c < 5; ++c) (v.R + c * Ev)[vi] = R[c];
     } else {
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        const int64_t ix = ((int64_t)c * E + e) * n3 + a;
-        const double du = v.rkA * v.dU[ix] + v.dt * R[c];
-        v.dU[ix] = du;
-        Unew[c] = v.U[ix] + v.rkB * du;
-        v.U[ix] = Unew[c];
+        double *dUc = v.dU + c * Ev;
+        const double du = v.rkA * dUc[vi] + v.dt * R[c];
+        dUc[vi] = du;
+        Unew[c] = Uold[c] + v.rkB * du;
+        (v.U + c * Ev)[vi] = Unew[c];
       }
     }
   }
   if (mode == 0) {
-    // ProlongToFace of the updated state for the next stage
+    // ProlongToFace of the updated state for the next stage (the last
+    // barrier of the volume integral precedes these writes)
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) sB[le][c][a] = (real)Unew[c];
+      for (int c = 0; c < 5; ++c) sm[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Unew[c];
     }
     __syncthreads();
     if (active) {
       real *trn = v.cur ? v.Utr0 : v.Utr1;
       for (int fn = a; fn < nf; fn += n3) {
-        const int f = fn / n2, pq = fn - f * n2, d = f >> 1, p = pq % n, q = pq / n;
-        const real *lv = (f & 1) ? sb.lp : sb.lm;
+        const int f = fn / n2, pq = fn - f * n2;
+        int base, stride;
+        Pad<n>::face_line(f, pq, base, stride);
+        real t[5];
+        prolong_state<n>(sm, (f & 1) ? sb.lp : sb.lm, base, stride, t);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          real s = real(0);
-#pragma unroll
-          for (int l = 0; l < n; ++l) s += lv[l] * sB[le][c][lnode<n>(d, l, p, q)];
-          trn[(int64_t)c * Ef + (e * 6) * n2 + fn] = s;
-        }
+        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Viscous operator without shock capturing, in two sweeps that exchange as
-// little as possible through HBM:
-//   k_volume : the BR1 lifting of k_lift with g kept on chip.  From the
-//              lifted gradient it forms (a) at each own face node this side's
-//              viscous normal flux H = F_v(prim, g) . n, with n in the primary
-//              side's orientation, and (b) at the volume nodes the complete
-//              volume integral of F_adv - F_v (VolInt).  Writes H (4 values
-//              per face node: the mass component is zero) and the volume
-//              integral (5 per node).
-//   k_surface: FillFlux from both sides' U traces and both sides' H (the
-//              BR1 viscous face flux is the mean of the two H), the SurfInt
-//              gather, ApplyJac, the stage update and the next U traces.
-// Both sweeps evaluate the same expressions in the same order as k_lift +
-// k_rhs.  Between the sweeps 5 volume and 4 face values per node cross HBM
-// instead of 12 and 12, and the metrics are read once per stage.
+// FV subcell volume term of one element (Sec. 2.3).  Subcells sit on the
+// Lobatto nodes with interfaces at the cumulative weights; the interface
+// metric accumulates w_m (D Ja)_m along each line from the element face;
+// primitives are reconstructed with minmod slopes (zero in the two boundary
+// subcells) and joined by the LLF flux.  `rows` are 16 LDS rows of n3 values
+// of this element: 0-4 primitives, 5-7 the metric of one direction, 8-10
+// w_l (D Ja)_l, 11-15 interface fluxes.  sFV holds D, w, x, xhalf.  Every
+// thread of the workgroup calls it: it holds barriers.  Adds the subcell
+// term at this node to Vfv (the sign convention of the DG volume integral).
 // ---------------------------------------------------------------------------
+template <int N, typename real>
+__device__ __forceinline__ void fv_subcells(real *rows, const real *sFV, bool active, int a, int i, int j, int k,
+                                            const real *P, const real *Ja, real gam, real rR, real *Vfv) {
+  constexpr int n = N + 1, n3 = n * n * n;
+  const real *Dm = sFV;
+  const real *wq = sFV + n * n;
+  const real *xq = sFV + n * n + n;
+  const real *xh = sFV + n * n + 2 * n;
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) rows[c * n3 + a] = P[c];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int l = d == 0 ? i : (d == 1 ? j : k);
+    const int pp = d == 0 ? j : i, qq = d == 2 ? j : k;
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rows[(5 + c) * n3 + a] = Ja[3 * d + c];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        real s = real(0);
+#pragma unroll
+        for (int m = 0; m < n; ++m) s += Dm[l * n + m] * rows[(5 + c) * n3 + lnode<n>(d, m, pp, qq)];
+        rows[(8 + c) * n3 + a] = wq[l] * s;
+      }
+    }
+    __syncthreads();
+    if (active && l < N) {
+      real Jh[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        real acc = rows[(5 + c) * n3 + lnode<n>(d, 0, pp, qq)];
+        for (int m = 0; m <= l; ++m) acc += rows[(8 + c) * n3 + lnode<n>(d, m, pp, qq)];
+        Jh[c] = acc;
+      }
+      const real sh = sqrt(Jh[0] * Jh[0] + Jh[1] * Jh[1] + Jh[2] * Jh[2]);
+      const real nv[3] = {Jh[0] / sh, Jh[1] / sh, Jh[2] / sh};
+      real qL[5], qR[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const real q0 = rows[c * n3 + lnode<n>(d, l, pp, qq)];
+        const real q1 = rows[c * n3 + lnode<n>(d, l + 1, pp, qq)];
+        real s0 = real(0), s1 = real(0);
+        if (l >= 1) {
+          const real qm = rows[c * n3 + lnode<n>(d, l - 1, pp, qq)];
+          s0 = minmod2((q0 - qm) / (xq[l] - xq[l - 1]), (q1 - q0) / (xq[l + 1] - xq[l]));
+        }
+        if (l + 1 <= N - 1) {
+          const real q2 = rows[c * n3 + lnode<n>(d, l + 2, pp, qq)];
+          s1 = minmod2((q1 - q0) / (xq[l + 1] - xq[l]), (q2 - q1) / (xq[l + 2] - xq[l + 1]));
+        }
+        qL[c] = q0 + s0 * (xh[l + 1] - xq[l]);
+        qR[c] = q1 - s1 * (xq[l + 1] - xh[l + 1]);
+      }
+      real UL[5], UR[5], PL[6], PR[6], F[5];
+      prim2cons(qL, gam, UL);
+      prim2cons(qR, gam, UR);
+      cons2prim(UL, gam, rR, PL);
+      cons2prim(UR, gam, rR, PR);
+      riemann_llf(UL, PL, UR, PR, nv, gam, F);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) rows[(11 + c) * n3 + a] = F[c] * sh;
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        real r = real(0);
+        if (l < N) r += rows[(11 + c) * n3 + a];
+        if (l > 0) r -= rows[(11 + c) * n3 + lnode<n>(d, l - 1, pp, qq)];
+        Vfv[c] += r / wq[l];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int N>
 struct VolLds {
   using S = Sz<N>;
@@ -778,7 +517,15 @@ struct VolLds {
   static_assert(12 * gsz <= Ns, "g must not cover n shat");
 };
 
-template <int N, typename real, bool BATCH>
+// ---------------------------------------------------------------------------
+// Volume sweep.  From the lifted gradient, which never leaves the chip, it
+// forms (a) at each own face node this side's viscous normal flux
+// H = F_v(prim, g).n, with n in the primary side's orientation, and (b) the
+// complete volume integral of F_adv - F_v.  Writes H (4 values per face node:
+// the mass component is zero) and the volume integral (5 per node); with
+// shock capturing also the element's indicator value.
+// ---------------------------------------------------------------------------
+template <int N, typename real, bool BATCH, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const View<real> *views, const int *blk_start,
                                                                          int nreq, View<real> single) {
   using S = Sz<N>;
@@ -798,6 +545,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
   const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
   const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
+  const bool visc = v.viscous != 0;  // the same for the whole grid
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
   // when a wave is one k-plane of one element (n^2 = 64), the k row of D-hat
@@ -816,6 +564,25 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   if (active) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = (real)(v.U + c * Ev)[vi];
+  }
+  if constexpr (SHOCK) {
+    // a-priori indicator of this element (Sec. 2.3) on epsilon = rho p, in the
+    // metric rows before they are filled; its neighbour propagation follows in
+    // the surface sweep
+    real eps = real(0);
+    if (active) {
+      real P[6];
+      cons2prim(U, gam, rR, P);
+      eps = P[0] * P[4];
+    }
+    const BasisOffsets o(n);
+    real *r = sm + L::J;
+    const real al = indicator_raw<N, real>(v, v.basis + o.Vinv, r, r + n3, r + 2 * n3, r + 3 * n3, r + 4 * n3,
+                                           r + 5 * n3, active, a, eps);
+    if (active && a == 0) v.alpha_raw[e] = al;
+    __syncthreads();
+  }
+  if (active) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + a] = (v.Ja + c * Ev)[vi];
     real P[6];
@@ -824,6 +591,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     sm[L::V + 1 * n3 + a] = P[2];
     sm[L::V + 2 * n3 + a] = P[3];
     sm[L::V + 3 * n3 + a] = P[5];
+  }
+  if (active && visc) {
     // Lift_FillFlux: the BR1 average of both sides' traces, and this side's
     // outward n shat and face velocity for its viscous flux later on
 #pragma unroll
@@ -859,7 +628,9 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   __syncthreads();
   real Fc[15];  // contravariant fluxes Ja^i . (F_adv - F_v), i = 0..2
   real g[12];
-  if (active) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) g[c] = real(0);
+  if (active && visc) {
     // Lift_VolInt along the three computational directions
     real JG[12];
 #pragma unroll
@@ -900,21 +671,26 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     const real iJ = v.invJ[vi];
 #pragma unroll
     for (int c = 0; c < 12; ++c) g[c] = JG[c] * iJ;
+  }
+  if (active) {
     // volume fluxes at this node, projected on the three contravariant directions
     real P[6];
     cons2prim(U, gam, rR, P);
-    real Fx[5], Fy[5], Fz[5], Vx[5], Vy[5], Vz[5];
+    real Fx[5], Fy[5], Fz[5];
     flux_adv<0>(U, P, Fx);
     flux_adv<1>(U, P, Fy);
     flux_adv<2>(U, P, Fz);
-    flux_visc<0>(P, g, mu, lam, Vx);
-    flux_visc<1>(P, g, mu, lam, Vy);
-    flux_visc<2>(P, g, mu, lam, Vz);
+    if (visc) {
+      real Vx[5], Vy[5], Vz[5];
+      flux_visc<0>(P, g, mu, lam, Vx);
+      flux_visc<1>(P, g, mu, lam, Vy);
+      flux_visc<2>(P, g, mu, lam, Vz);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      Fx[c] -= Vx[c];
-      Fy[c] -= Vy[c];
-      Fz[c] -= Vz[c];
+      for (int c = 0; c < 5; ++c) {
+        Fx[c] -= Vx[c];
+        Fy[c] -= Vy[c];
+        Fz[c] -= Vz[c];
+      }
     }
 #pragma unroll
     for (int ci = 0; ci < 3; ++ci) {
@@ -925,13 +701,13 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     }
   }
   __syncthreads();  // the rows read above are covered by g below
-  if (active) {
+  if (active && visc) {
     const int pa = Pad<n>::at(i, j, k);
 #pragma unroll
     for (int c = 0; c < 12; ++c) sm[L::G + c * L::gsz + pa] = g[c];
   }
   __syncthreads();
-  if (active) {
+  if (active && visc) {
     // Lift_ProlongToFace of g, then this side's viscous normal flux
 #pragma unroll
     for (int r = 0; r < L::fpt; ++r) {
@@ -1003,7 +779,13 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   }
 }
 
-template <int N, typename real, bool BATCH>
+// ---------------------------------------------------------------------------
+// Surface sweep: FillFlux from this side's recomputed U trace, the
+// neighbour's stored one and the mean of both sides' H; with shock capturing
+// the blend of the FV subcell operator; SurfInt gather, ApplyJac, the stage
+// update (mode 0) or R (mode 1), and the next U traces.
+// ---------------------------------------------------------------------------
+template <int N, typename real, bool BATCH, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
                                                                           int nreq, View<real> single, int mode) {
   using S = Sz<N>;
@@ -1013,13 +795,30 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
   __shared__ Smem<N, real> sb;
   __shared__ real sB[epb][5][Pad<n>::size];
   __shared__ real sS[epb][5][nf];
+  // shock capturing: 16 rows per element for the subcell operator and the
+  // advective volume integral, the 1-D operators of the subcells, alpha
+  __shared__ real sX[SHOCK ? epb * 16 * n3 : 1];
+  __shared__ real sFV[SHOCK ? (n * n + 3 * n + 1) : 1];  // D, w, x, xhalf
+  __shared__ real sAl[epb];
+  __shared__ int sAny;
   load_basis<N, real>(sb, v.basis);
+  if constexpr (SHOCK) {
+    const BasisOffsets o(n);
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) sFV[t] = v.basis[o.D + t];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      sFV[n * n + t] = v.basis[o.w + t];
+      sFV[n * n + n + t] = v.basis[o.x + t];
+    }
+    for (int t = threadIdx.x; t < n + 1; t += blockDim.x) sFV[n * n + 2 * n + t] = v.basis[o.xhalf + t];
+    if (threadIdx.x == 0) sAny = 0;
+  }
   const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
   const int64_t e = (int64_t)lblk * epb + le;
   const bool active = le < epb && e < v.E;
   const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
   const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
   const real gam = v.gamma, rR = v.rRgas;
+  const bool visc = v.viscous != 0;  // the same for the whole grid
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
   constexpr bool plane_waves = n2 == 64 && epb == 1;  // a wave is one face of one element
@@ -1032,8 +831,30 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
       Uold[c] = (v.U + c * Ev)[vi];
       su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Uold[c];
     }
+    if (SHOCK && a == 0) {
+      // blending factor: frozen, or the element's indicator value raised to
+      // half of its face neighbours' (Sec. 2.3)
+      real a0;
+      if (v.alpha_in) {
+        a0 = v.alpha_in[e];
+      } else {
+        a0 = v.alpha_raw[e];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) a0 = fmax(a0, real(0.5) * v.alpha_raw[v.conn[e * 6 + f].x / 6]);
+        a0 = fmin(a0, v.alpha_max);
+      }
+      sAl[le] = a0;
+    }
   }
   __syncthreads();
+  real al = real(0);
+  if constexpr (SHOCK) {
+    if (active) {
+      al = sAl[le];
+      if (a == 0) v.alpha[e] = al;
+      if (al > real(0)) sAny = 1;  // every writer stores 1; read after the next barrier
+    }
+  }
   if (active) {
     // FillFlux: Riemann flux of the U traces minus the mean of both sides' H.
     // This side's trace is recomputed from the state (the same bits as the
@@ -1075,18 +896,67 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
       real Fs[5];
       if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs);
       else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs);
+      if (visc) {
 #pragma unroll
-      for (int s = 1; s < 5; ++s) Fs[s] -= real(0.5) * ((v.Hv + (s - 1) * Ef)[im] + (v.Hv + (s - 1) * Ef)[is]);
+        for (int s = 1; s < 5; ++s) Fs[s] -= real(0.5) * ((v.Hv + (s - 1) * Ef)[im] + (v.Hv + (s - 1) * Ef)[is]);
+      }
 #pragma unroll
       for (int s = 0; s < 5; ++s) sS[le][s][fn] = primary ? Fs[s] * sh : -(Fs[s] * sh);
     }
   }
   __syncthreads();
+  // blended elements: alpha (V_FV - V_adv) joins the stored volume integral,
+  // i.e. (1 - alpha) V_adv + alpha V_FV + V_visc
+  real Vb[5] = {0, 0, 0, 0, 0};
+  if constexpr (SHOCK) {
+    if (sAny) {  // the same on every thread of the workgroup
+      real *rows = sX + (le < epb ? le : 0) * 16 * n3;
+      real U[5], P[6], Ja[9];
+      if (active) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) U[c] = (real)Uold[c];
+        cons2prim(U, gam, rR, P);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Ja[c] = (v.Ja + c * Ev)[vi];
+      }
+      real Vfv[5] = {0, 0, 0, 0, 0};
+      fv_subcells<N, real>(rows, sFV, active, a, i, j, k, P, Ja, gam, rR, Vfv);
+      // the advective DG volume integral, the three directions at once
+      if (active) {
+        real Fx[5], Fy[5], Fz[5];
+        flux_adv<0>(U, P, Fx);
+        flux_adv<1>(U, P, Fy);
+        flux_adv<2>(U, P, Fz);
+#pragma unroll
+        for (int ci = 0; ci < 3; ++ci)
+#pragma unroll
+          for (int c = 0; c < 5; ++c)
+            rows[(5 * ci + c) * n3 + a] = Ja[3 * ci + 0] * Fx[c] + Ja[3 * ci + 1] * Fy[c] + Ja[3 * ci + 2] * Fz[c];
+      }
+      __syncthreads();
+      if (active && al > real(0)) {
+        real Va[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int ci = 0; ci < 3; ++ci) {
+          const int idx = ci == 0 ? i : (ci == 1 ? j : k);
+#pragma unroll
+          for (int alp = 0; alp < n; ++alp) {
+            const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
+            const real dh = sb.Dh[idx * (n + 1) + alp];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Va[c] += dh * rows[(5 * ci + c) * n3 + src];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Vb[c] = al * (Vfv[c] - Va[c]);
+      }
+    }
+  }
   double Unew[5] = {0, 0, 0, 0, 0};
   if (active) {
     real V[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) V[c] = (v.Vol + c * Ev)[vi];
+    for (int c = 0; c < 5; ++c) V[c] = (v.Vol + c * Ev)[vi] + Vb[c];
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -1297,29 +1167,34 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
       else k_trace<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       break;
     case K_LIFT:
-      // shock capturing: indicator (+ lifting with g stored); viscous: the split volume sweep
+      // volume sweep: indicator (shock capturing), lifting (viscous), VolInt
       if (v0.shock) {
-        if (batch) k_lift<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-        else k_lift<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
+          if (batch) k_volume<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+          else k_volume<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        } else {
+          return hipErrorInvalidValue;
+        }
       } else {
-        if (batch) k_volume<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-        else k_volume<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        if (batch) k_volume<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        else k_volume<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       }
       break;
     case K_RHS:
+      // surface sweep (after a volume sweep), or the one-sweep Euler operator
       if (v0.shock) {
-        if constexpr (N >= 2) {
-          if (batch) k_rhs<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-          else k_rhs<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
+          if (batch) k_surface<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          else k_surface<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
         } else {
           return hipErrorInvalidValue;
         }
       } else if (v0.viscous) {
-        if (batch) k_surface<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-        else k_surface<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        if (batch) k_surface<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        else k_surface<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       } else {
-        if (batch) k_rhs<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-        else k_rhs<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        if (batch) k_rhs<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        else k_rhs<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       }
       break;
     default: return hipErrorInvalidValue;

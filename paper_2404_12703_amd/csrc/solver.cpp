@@ -77,11 +77,10 @@ Layout make_layout(const dg_params &p, int64_t E) {
   L.NS = take(3 * E * 6 * n2 * rs);
   L.Utr0 = take(5 * E * 6 * n2 * rs);
   L.Utr1 = take(5 * E * 6 * n2 * rs);
-  // shock capturing keeps g and its traces (12 rows each); the split viscous
-  // path stores one side's viscous face flux (4 rows) and the volume integral (5)
-  const int64_t gtr_rows = p.shock_capturing ? 12 : 4, g_rows = p.shock_capturing ? 12 : 5;
-  L.Gtr = p.viscous ? take(gtr_rows * E * 6 * n2 * rs) : SIZE_MAX;
-  L.G = p.viscous ? take(g_rows * E * n3 * rs) : SIZE_MAX;
+  // the two sweeps exchange each side's viscous face flux (4 values per face
+  // node, viscous only) and the volume integral (5 per node)
+  L.Hv = p.viscous ? take(4 * E * 6 * n2 * rs) : SIZE_MAX;
+  L.Vol = (p.viscous || p.shock_capturing) ? take(5 * E * n3 * rs) : SIZE_MAX;
   L.conn = take(6 * E * sizeof(int2));
   L.Xs = p.source ? take(3 * E * n3 * 8) : SIZE_MAX;
   L.basis = take(BasisOffsets(n).total * rs);
@@ -106,10 +105,8 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.NS = (const real *)at(L.NS);
   v.Utr0 = (real *)at(L.Utr0);
   v.Utr1 = (real *)at(L.Utr1);
-  v.Gtr = (real *)at(L.Gtr);
-  v.G = (real *)at(L.G);
-  v.Hv = v.Gtr;
-  v.Vol = v.G;
+  v.Hv = (real *)at(L.Hv);
+  v.Vol = (real *)at(L.Vol);
   v.conn = (const int2 *)at(L.conn);
   v.Xs = (const double *)at(L.Xs);
   v.basis = (const real *)at(L.basis);

@@ -156,3 +156,45 @@ def test_full_size_blast_32cubed_one_step():
     Uo = o.advance(wl.U0, dt, 1)
     assert np.isfinite(Uo).all()
     assert rel(s.state(), Uo) <= 1e-12
+
+
+def test_inviscid_blast_parity():
+    """shock capturing without viscosity: the volume sweep skips the lifting
+    and the viscous face flux"""
+    wl = _blast(4, 4, rotate=True)
+    p = dict(wl.params)
+    p["viscous"] = 0
+    _say("[inviscid blast] K=4 N=4")
+    o = O.Oracle(p, wl.mesh)
+    s = _solver(p, wl.mesh)
+    s.set_state(wl.U0)
+    Rg = s.rhs(0.0)
+    Ro = o.rhs(wl.U0, 0.0)
+    ag, ao = s.alpha(), o.alpha()
+    assert (ao > 0).any() and (ao == 0).any()
+    assert np.sum((ag > 0) != (ao > 0)) == 0
+    assert np.abs(ag - ao).max() <= 1e-10
+    assert rel(Rg, Ro) <= 1e-12
+    dt = o.stable_dt(wl.U0, wl.cfl, wl.cfl)
+    s.advance(3, dt)
+    Uo = o.advance(wl.U0, dt, 3)
+    assert rel(s.state(), Uo) <= 1e-12
+    assert rel(s.state() - wl.U0, Uo - wl.U0) <= 1e-9
+
+
+@pytest.mark.parametrize("viscous", [0, 1])
+def test_blend_with_mixed_alpha_in_one_workgroup(viscous):
+    """N = 2 puts nine elements in a workgroup: blended and unblended elements
+    share the subcell pass, each keeps its own factor"""
+    m = W.box_mesh(3, 0.0, 2 * np.pi, 2, amp=0.05, rotate=True)
+    p = W.params(2, node_type=1, riemann=0, viscous=viscous, shock=1, mu=1e-2)
+    X = m.points(W.lgl_points(2))
+    U = W.random_smooth_state(X, 11, 1.4, m.period)
+    alpha = np.zeros(m.n_elems)
+    alpha[::4] = np.random.default_rng(3).uniform(0.2, 1.0, len(alpha[::4]))
+    o = O.Oracle(p, m)
+    o.set_alpha(alpha)
+    s = _solver(p, m)
+    s.set_alpha(alpha)
+    s.set_state(U)
+    assert rel(s.rhs(0.0), o.rhs(U, 0.0)) <= 1e-12
