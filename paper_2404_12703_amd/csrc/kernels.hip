@@ -38,8 +38,9 @@ struct Sz {
   static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, nf = 6 * n2;
   static constexpr int epb = (256 / n3) > 1 ? 256 / n3 : 1;  // elements per workgroup
   static constexpr int threads = ((epb * n3 + 63) / 64) * 64;
-  // waves per SIMD to plan registers for: two 512-thread workgroups per CU
-  static constexpr int minw = threads == 512 ? 4 : 1;
+  // waves per SIMD to plan registers for (128 VGPRs): two 512-thread or four
+  // 256-thread workgroups per CU
+  static constexpr int minw = (threads == 512 || threads == 256) ? 4 : 1;
 };
 
 __device__ __forceinline__ int vnode(int n, int i, int j, int k) { return i + n * (j + n * k); }
