@@ -123,14 +123,18 @@ def solve_latency(P, wl, steps, repeats, cfl=None, dt=None):
 def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30, max_active=64):
     """the served stream: nreq seeded requests (K in 4..16, N in {3,5,7},
     Ma, Re, steps drawn per request) with Poisson arrivals at `load` times the
-    measured throughput, FIFO admission under an HBM budget.  Returns
-    throughput over the makespan and p50/p99 of t_done - t_arrival."""
+    measured throughput (load None: all at t = 0), FIFO admission under an
+    HBM budget.  Returns throughput over the makespan and p50/p99 of
+    t_done - t_arrival."""
     import torch
     base = W.serving_requests(nreq, seed, rate=1.0)
     work = [(r["K"] ** 3) * (r["N"] + 1) ** 3 * 5 * r["steps"] for r in base]
-    lam = load * throughput / float(np.mean(work))
-    g = np.random.default_rng(seed + 1000)
-    arrivals = np.cumsum(g.exponential(1.0 / lam, size=nreq))
+    if load is None:  # every request arrives at t = 0
+        arrivals = np.zeros(nreq)
+    else:
+        lam = load * throughput / float(np.mean(work))
+        g = np.random.default_rng(seed + 1000)
+        arrivals = np.cumsum(g.exponential(1.0 / lam, size=nreq))
     arena = min(budget + (256 << 20), int(torch.cuda.mem_get_info()[0] * 0.8))
     sv = P.Server(arena_bytes=arena, hbm_budget=budget, max_active=max_active)
     ids = []
@@ -146,7 +150,7 @@ def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30,
         ok += tm["state"] == P.REQ_DONE
         lat.append(tm["t_done"] - tm["t_arrival"])
     sv.close()
-    return dict(requests=nreq, done=ok, load=load, precision=precision,
+    return dict(requests=nreq, done=ok, load=("all at t=0" if load is None else load), precision=precision,
                 value=float(np.sum(work)) / makespan, unit="DOF*stage/s",
                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 makespan_s=makespan, budget_GB=budget / 2 ** 30)
@@ -270,7 +274,9 @@ def main():
         line["blast32"] = st
         del sbl
         torch.cuda.empty_cache()
-        line["served"] = [served(P, W, args.serve_requests, 0, value, precision=pr) for pr in (0, 1)]
+        line["served"] = [served(P, W, args.serve_requests, 0, value, load=ld, precision=0)
+                          for ld in (0.5, 0.8, 1.2, None)]
+        line["served"].append(served(P, W, args.serve_requests, 0, value, load=0.8, precision=1))
     if not args.no_cpu and not args.only_main:
         line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1))
     print(json.dumps(line), flush=True)

@@ -16,12 +16,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -33,6 +36,8 @@ using namespace dg;
 namespace {
 
 constexpr int kDescSlots = 16;  // ring of descriptor uploads in flight
+constexpr int kPrepAhead = 16;  // requests at the head of the queue prepared ahead of admission
+enum { PREP_WAITING = 0, PREP_RUNNING = 1, PREP_READY = 2, PREP_FAILED = 3 };
 
 struct Request {
   int64_t id = 0;
@@ -55,7 +60,11 @@ struct Request {
   int step = 0, stage = 0, cur = 0;
   double t = 0.0;
   bool traces_valid = false;
-  std::unique_ptr<Staging> staging;
+  // host set-up, made by the preparation thread once the request has arrived;
+  // kept until its upload has landed
+  std::unique_ptr<HostSetup> host;
+  std::atomic<int> prep{PREP_WAITING};
+  std::string prep_err;
   hipEvent_t ready = nullptr;  // set-up copies done
   // retirement
   std::vector<double> result;
@@ -119,8 +128,13 @@ struct dg_server {
   hipEvent_t desc_ev[kDescSlots] = {};
   int desc_next = 0;
   int *flags_dev = nullptr;
+  // reqs and queue are shared with the preparation thread: changed under prep_mu
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::deque<int64_t> queue;
+  std::mutex prep_mu;
+  std::condition_variable prep_cv;
+  bool prep_stop = false;
+  std::thread prep_thread;
   std::vector<int64_t> active;
   int64_t next_id = 1;
   std::chrono::steady_clock::time_point t0;
@@ -137,56 +151,95 @@ dg_status server_fail(dg_server *sv, hipError_t e, const char *what) {
   return fail(DG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// The preparation thread: host set-up (geometry, metrics, the CFL step) of
+// the requests near the head of the queue that have arrived, in queue order,
+// while the serving loop keeps the GPU busy.
+void prep_loop(dg_server *sv) {
+  std::unique_lock<std::mutex> lk(sv->prep_mu);
+  while (!sv->prep_stop) {
+    Request *next = nullptr;
+    double wake = 1e300;
+    int pos = 0;
+    for (int64_t id : sv->queue) {
+      if (pos++ >= kPrepAhead) break;
+      Request &r = *sv->reqs[id];
+      if (r.prep.load(std::memory_order_acquire) != PREP_WAITING) continue;
+      if (r.t_arrival <= sv->now()) {
+        next = &r;
+        break;
+      }
+      wake = std::min(wake, r.t_arrival);
+    }
+    if (!next) {
+      if (wake < 1e300)
+        sv->prep_cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, wake - sv->now())));
+      else
+        sv->prep_cv.wait(lk);
+      continue;
+    }
+    next->prep.store(PREP_RUNNING, std::memory_order_relaxed);
+    lk.unlock();
+    std::unique_ptr<HostSetup> hs(new HostSetup());
+    dg_mesh m{next->E, next->n_geo, 0, next->x_geo.data(), next->nbr_elem.data(), next->nbr_face.data(),
+              next->nbr_orient.data()};
+    std::string err;
+    const dg_status rc = setup_host(next->p, m, next->U0.data(), next->dt < 0.0 ? -next->dt : 0.0, *hs, err);
+    lk.lock();
+    if (rc == DG_OK) {
+      if (next->dt < 0.0) next->dt = hs->dt;
+      next->host = std::move(hs);
+      next->prep.store(PREP_READY, std::memory_order_release);
+    } else {
+      next->prep_err = err;
+      next->prep.store(PREP_FAILED, std::memory_order_release);
+    }
+  }
+}
+
 // admit the head of the queue while it fits
 dg_status admit(dg_server *sv) {
-  double now = sv->now();
-  while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active) {
-    Request &r = *sv->reqs[sv->queue.front()];
+  const double now = sv->now();
+  while ((int)sv->active.size() < sv->max_active) {
+    Request *rp;
+    {
+      std::lock_guard<std::mutex> lk(sv->prep_mu);
+      if (sv->queue.empty()) break;
+      rp = sv->reqs.at(sv->queue.front()).get();
+    }
+    Request &r = *rp;
     if (r.t_arrival > now) break;
+    const int ps = r.prep.load(std::memory_order_acquire);
+    if (ps == PREP_WAITING || ps == PREP_RUNNING) break;  // its set-up is still being made
+    if (ps == PREP_FAILED) {  // the mesh passed the checks at submit but not the geometric ones
+      {
+        std::lock_guard<std::mutex> lk(sv->prep_mu);
+        sv->queue.pop_front();
+      }
+      sv->prep_cv.notify_one();
+      std::vector<double>().swap(r.U0);
+      r.state = DG_REQ_FAILED;
+      r.t_done = now;
+      continue;
+    }
     size_t off;
     if (!sv->alloc.alloc(r.L.total, off)) break;  // wait for memory to free up
-    sv->queue.pop_front();
+    {
+      std::lock_guard<std::mutex> lk(sv->prep_mu);
+      sv->queue.pop_front();
+    }
+    sv->prep_cv.notify_one();  // the next request in line may be prepared now
     r.off = off;
     r.bytes = r.L.total;
     void *base = sv->arena + off;
     fill_view(r.vd, base, r.L, r.p, r.E);
     fill_view(r.vf, base, r.L, r.p, r.E);
-    dg_mesh m{r.E, r.n_geo, 0, r.x_geo.data(), r.nbr_elem.data(), r.nbr_face.data(), r.nbr_orient.data()};
-    r.staging.reset(new Staging());
-    dg_status rc = setup_upload(r.p, m, base, r.L, sv->cst, *r.staging);
-    hipError_t e = hipSuccess;
-    if (rc == DG_OK) {
-      r.staging->d.push_back(std::move(r.U0));
-      const std::vector<double> &u = r.staging->d.back();
-      e = hipMemcpyAsync((char *)base + r.L.U, u.data(), u.size() * 8, hipMemcpyHostToDevice, sv->cst);
-      if (e == hipSuccess && r.dt <= 0.0) {
-        // time step from the initial state: CFL = DFL = -dt (needs the value on the host now)
-        double *scr = (double *)((char *)base + r.L.scratch);
-        e = r.p.precision ? launch_dt<float>(r.p.N, r.vf, scr, kRedBlocks, sv->cst)
-                          : launch_dt<double>(r.p.N, r.vd, scr, kRedBlocks, sv->cst);
-        std::vector<double> h(2 * kRedBlocks);
-        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), scr, h.size() * 8, hipMemcpyDeviceToHost, sv->cst);
-        if (e == hipSuccess) e = hipStreamSynchronize(sv->cst);
-        double da = 1e300, dv = 1e300;
-        for (int b = 0; b < kRedBlocks; ++b) {
-          da = std::min(da, h[2 * b]);
-          dv = std::min(dv, h[2 * b + 1]);
-        }
-        const double cfl = -r.dt;
-        r.dt = std::min(cfl * da, cfl * dv);
-        if (!(r.dt > 0.0 && r.dt < 1e299)) rc = DG_ENONFINITE;
-      }
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventRecord(r.ready, sv->cst);
-      if (e == hipSuccess) e = hipStreamWaitEvent(sv->st, r.ready, 0);
-      if (e != hipSuccess) return server_fail(sv, e, "admission upload");
-    }
-    if (rc != DG_OK) {  // the mesh was validated at submit; a failure here retires the request
-      sv->alloc.release(r.off, r.bytes);
-      r.state = DG_REQ_FAILED;
-      r.t_done = sv->now();
-      continue;
-    }
+    hipError_t e = setup_device(r.p, *r.host, base, r.L, sv->cst);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((char *)base + r.L.U, r.U0.data(), r.U0.size() * 8, hipMemcpyHostToDevice, sv->cst);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r.ready, sv->cst);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sv->st, r.ready, 0);
+    if (e != hipSuccess) return server_fail(sv, e, "admission upload");
     r.state = DG_REQ_RUNNING;
     r.t_admit = sv->now();
     r.t = 0.0;
@@ -321,14 +374,17 @@ dg_status retire(dg_server *sv) {
       r.done_ev = nullptr;
       if (r.ready) (void)hipEventDestroy(r.ready);
       r.ready = nullptr;
-      r.staging.reset();
+      r.host.reset();
       sv->alloc.release(r.off, r.bytes);
       r.state = bad ? DG_REQ_FAILED : DG_REQ_DONE;
       r.t_done = sv->now();
       continue;
     }
-    // set-up staging can go once the uploads have landed
-    if (r.staging && r.ready && hipEventQuery(r.ready) == hipSuccess) r.staging.reset();
+    // the host set-up and initial state can go once their uploads have landed
+    if (r.host && r.ready && hipEventQuery(r.ready) == hipSuccess) {
+      r.host.reset();
+      std::vector<double>().swap(r.U0);
+    }
     keep.push_back(id);
   }
   sv->active.swap(keep);
@@ -363,6 +419,7 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
     if (e != hipSuccess) return fail(DG_EDEVICE, std::string("server set-up: ") + hipGetErrorString(e));
   }
   sv->t0 = std::chrono::steady_clock::now();
+  sv->prep_thread = std::thread(prep_loop, sv.get());
   *out = sv.release();
   return DG_OK;
 }
@@ -395,8 +452,12 @@ dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, 
   r->dt = dt;
   r->t_arrival = t_arrival;
   *req_id = r->id;
-  sv->queue.push_back(r->id);
-  sv->reqs[r->id] = std::move(r);
+  {
+    std::lock_guard<std::mutex> lk(sv->prep_mu);
+    sv->queue.push_back(r->id);
+    sv->reqs[r->id] = std::move(r);
+  }
+  sv->prep_cv.notify_one();
   return DG_OK;
 }
 
@@ -408,10 +469,15 @@ dg_status dg_server_run(dg_server *sv, int32_t max_ticks) {
     dg_status rc = admit(sv);
     if (rc) return rc;
     if (sv->active.empty()) {
-      if (sv->queue.empty()) break;
-      // nothing runs: wait for the next arrival
-      const double wait = sv->reqs[sv->queue.front()]->t_arrival - sv->now();
-      if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
+      double head_arrival;
+      {
+        std::lock_guard<std::mutex> lk(sv->prep_mu);
+        if (sv->queue.empty()) break;
+        head_arrival = sv->reqs.at(sv->queue.front())->t_arrival;
+      }
+      // nothing runs: wait for the next arrival, or for its set-up
+      const double wait = std::max(head_arrival - sv->now(), 0.0005);
+      std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
       if (max_ticks > 0 && ++ticks >= max_ticks) break;
       continue;
     }
@@ -451,6 +517,12 @@ dg_status dg_server_fetch(dg_server *sv, int64_t req_id, double *U_host, dg_timi
 
 void dg_server_destroy(dg_server *sv) {
   if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->prep_mu);
+    sv->prep_stop = true;
+  }
+  sv->prep_cv.notify_all();
+  if (sv->prep_thread.joinable()) sv->prep_thread.join();
   (void)hipStreamSynchronize(sv->st);
   if (sv->cst != sv->st) (void)hipStreamSynchronize(sv->cst);
   for (auto &kv : sv->reqs) {

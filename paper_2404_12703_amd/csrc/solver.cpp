@@ -142,48 +142,82 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
 template void fill_view<double>(View<double> &, void *, const Layout &, const dg_params &, int64_t);
 template void fill_view<float>(View<float> &, void *, const Layout &, const dg_params &, int64_t);
 
-// Host set-up of one solve and its upload into the workspace at `base`
-// (enqueued on st; the returned staging buffers must live until st has
-// passed the copies).
-dg_status setup_upload(const dg_params &p, const dg_mesh &m, void *base, const Layout &L, hipStream_t st,
-                       Staging &stg) {
+// Host set-up of one solve (no HIP calls), then its upload.
+dg_status setup_host(const dg_params &p, const dg_mesh &m, const double *U0, double cfl, HostSetup &hs,
+                     std::string &err) {
   Basis b = make_basis(p.N, p.nodes);
   Geometry g;
-  std::string err;
   dg_status rc = build_geometry(b, m, g, err);
-  if (rc) return fail(rc, err);
-  const bool mixed = p.precision == 1;
+  if (rc) return rc;
+  const int64_t E = m.n_elems;
+  const int n = p.N + 1, n3 = n * n * n;
   std::vector<double> invJ(g.J.size());
   for (size_t i = 0; i < g.J.size(); ++i) invJ[i] = 1.0 / g.J[i];
+  if (U0 && cfl > 0.0) {
+    // the time-step estimate of dg_stable_dt (App. A.5): convective
+    // 2/((2N+1) sum_i lambda_i) and, with viscosity, 4/((N+1)^4 nu sum_i (|Ja^i|/J)^2)
+    const double gam = p.gamma, nfac = std::pow((double)n, 4.0);
+    double dta = 1e300, dtv = 1e300;
+    for (int64_t e = 0; e < E; ++e)
+      for (int a = 0; a < n3; ++a) {
+        double U[5];
+        for (int c = 0; c < 5; ++c) U[c] = U0[((size_t)c * E + e) * n3 + a];
+        const double rho = U[0], ir = 1.0 / rho, u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
+        const double pr = (gam - 1.0) * (U[4] - 0.5 * rho * (u * u + v * v + w * w));
+        const double c = std::sqrt(gam * pr / rho), iJ = invJ[(size_t)e * n3 + a];
+        double lamsum = 0.0, vis = 0.0;
+        for (int ci = 0; ci < 3; ++ci) {
+          const double j0 = g.Ja[((size_t)(3 * ci) * E + e) * n3 + a], j1 = g.Ja[((size_t)(3 * ci + 1) * E + e) * n3 + a],
+                       j2 = g.Ja[((size_t)(3 * ci + 2) * E + e) * n3 + a];
+          const double nj = std::sqrt(j0 * j0 + j1 * j1 + j2 * j2);
+          lamsum += (std::fabs(u * j0 + v * j1 + w * j2) + c * nj) * iJ;
+          vis += (nj * iJ) * (nj * iJ);
+        }
+        dta = std::min(dta, 2.0 / ((2.0 * p.N + 1.0) * lamsum));
+        if (p.viscous && p.mu > 0) {
+          const double nu = std::max(4.0 / 3.0, gam / p.Pr) * p.mu / rho;
+          dtv = std::min(dtv, 4.0 / (nfac * nu * vis));
+        }
+      }
+    hs.dt = std::min(cfl * dta, cfl * dtv);
+  }
+  std::vector<double> blk = basis_block(b);
+  if (p.precision == 1) {
+    auto to_f = [](const std::vector<double> &x) {
+      std::vector<float> f(x.size());
+      for (size_t i = 0; i < x.size(); ++i) f[i] = (float)x[i];
+      return f;
+    };
+    hs.fJa = to_f(g.Ja);
+    hs.finvJ = to_f(invJ);
+    hs.fNS = to_f(g.NS);
+    hs.fbasis = to_f(blk);
+  } else {
+    hs.Ja = std::move(g.Ja);
+    hs.invJ = std::move(invJ);
+    hs.NS = std::move(g.NS);
+    hs.basis = std::move(blk);
+  }
+  hs.conn = std::move(g.conn);
+  if (p.source) hs.Xs = std::move(g.Xs);
+  return DG_OK;
+}
+
+hipError_t setup_device(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st) {
   char *ws = (char *)base;
-  auto put = [&](size_t off, std::vector<double> &&h) -> hipError_t {
-    if (!mixed) {
-      stg.d.push_back(std::move(h));
-      const std::vector<double> &x = stg.d.back();
-      return hipMemcpyAsync(ws + off, x.data(), x.size() * 8, hipMemcpyHostToDevice, st);
-    }
-    std::vector<float> f(h.size());
-    for (size_t i = 0; i < h.size(); ++i) f[i] = (float)h[i];
-    stg.f.push_back(std::move(f));
-    const std::vector<float> &x = stg.f.back();
-    return hipMemcpyAsync(ws + off, x.data(), x.size() * 4, hipMemcpyHostToDevice, st);
+  const bool mixed = p.precision == 1;
+  auto put = [&](size_t off, const std::vector<double> &d, const std::vector<float> &f) -> hipError_t {
+    return mixed ? hipMemcpyAsync(ws + off, f.data(), f.size() * 4, hipMemcpyHostToDevice, st)
+                 : hipMemcpyAsync(ws + off, d.data(), d.size() * 8, hipMemcpyHostToDevice, st);
   };
   hipError_t e = hipMemsetAsync(ws, 0, L.total, st);
-  if (e == hipSuccess) e = put(L.Ja, std::move(g.Ja));
-  if (e == hipSuccess) e = put(L.invJ, std::move(invJ));
-  if (e == hipSuccess) e = put(L.NS, std::move(g.NS));
-  if (e == hipSuccess) e = put(L.basis, basis_block(b));
-  if (e == hipSuccess) {
-    stg.c = std::move(g.conn);
-    e = hipMemcpyAsync(ws + L.conn, stg.c.data(), stg.c.size() * sizeof(int2), hipMemcpyHostToDevice, st);
-  }
-  if (e == hipSuccess && p.source) {
-    stg.d.push_back(std::move(g.Xs));
-    const std::vector<double> &x = stg.d.back();
-    e = hipMemcpyAsync(ws + L.Xs, x.data(), x.size() * 8, hipMemcpyHostToDevice, st);
-  }
-  if (e != hipSuccess) return fail(DG_EDEVICE, std::string("set-up upload: ") + hipGetErrorString(e));
-  return DG_OK;
+  if (e == hipSuccess) e = put(L.Ja, hs.Ja, hs.fJa);
+  if (e == hipSuccess) e = put(L.invJ, hs.invJ, hs.finvJ);
+  if (e == hipSuccess) e = put(L.NS, hs.NS, hs.fNS);
+  if (e == hipSuccess) e = put(L.basis, hs.basis, hs.fbasis);
+  if (e == hipSuccess) e = hipMemcpyAsync(ws + L.conn, hs.conn.data(), hs.conn.size() * sizeof(int2), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && p.source) e = hipMemcpyAsync(ws + L.Xs, hs.Xs.data(), hs.Xs.size() * 8, hipMemcpyHostToDevice, st);
+  return e;
 }
 
 // upload a host FP64 array into device memory of the solve's arithmetic type
@@ -321,10 +355,12 @@ dg_status dg_create(const dg_params *p, const dg_mesh *m, void *d_workspace, siz
 
   fill_view(s->vd, s->ws, L, *p, s->E);
   fill_view(s->vf, s->ws, L, *p, s->E);
-  Staging stg;
-  rc = setup_upload(*p, *m, s->ws, L, s->st, stg);
-  if (rc) return rc;
-  hipError_t e = hipStreamSynchronize(s->st);  // staging buffers go out of scope
+  HostSetup hs;
+  std::string err;
+  rc = setup_host(*p, *m, nullptr, 0.0, hs, err);
+  if (rc) return fail(rc, err);
+  hipError_t e = setup_device(*p, hs, s->ws, L, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);  // the host buffers go out of scope
   if (e != hipSuccess) return device_error(nullptr, e, "dg_create upload");
   s->t = 0.0;
   s->cur = 0;

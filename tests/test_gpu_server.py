@@ -2,6 +2,7 @@
 must equal the same request run alone through a plain solver (bitwise: a
 request's arithmetic does not depend on the rest of the batch), for FP64 and
 the mixed form; a poisoned request fails alone; admission waits for memory."""
+import copy
 import sys
 
 import numpy as np
@@ -107,3 +108,28 @@ def test_arrivals_are_admitted_while_others_run():
     late_admit = min(t["t_admit"] for t in tms[3:])
     assert all(t["state"] == P.REQ_DONE for t in tms)
     assert late_admit < first_done  # a late arrival ran alongside the early ones
+
+
+def test_cfl_step_and_broken_mesh():
+    """dt < 0 asks for the stable step on the initial state (computed on the
+    host while the request is prepared): the result matches a plain solver
+    advanced with its own stable step.  A mesh whose neighbour table is not
+    symmetric passes the size checks at submit, fails its set-up, and ends
+    FAILED without disturbing the others."""
+    import paper_2404_12703_amd as P
+    reqs = _requests(4, 7, precision_mix=False)
+    _say("[server] CFL step and a broken mesh")
+    sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=4)
+    ids = [sv.submit(wl.params, wl.mesh, wl.U0, wl.steps, -0.9, 0.0) for _, wl in reqs]
+    bad_req, bad = reqs[0]
+    m = copy.copy(bad.mesh)
+    m.nbr_elem = m.nbr_elem.copy()
+    m.nbr_elem[0, 0] = 0  # element 0 names itself across its xi- face; its xi+ face disagrees
+    bad_id = sv.submit(bad.params, m, bad.U0, bad.steps, -0.9, 0.0)
+    sv.run(0)
+    assert sv.poll(bad_id) == P.REQ_FAILED
+    for (req, wl), rid in zip(reqs, ids):
+        assert sv.poll(rid) == P.REQ_DONE
+        U, _ = sv.fetch(rid)
+        ref = _alone(wl, _dt(wl))
+        assert np.linalg.norm(U - ref) <= 1e-12 * np.linalg.norm(ref), req
