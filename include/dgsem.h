@@ -195,11 +195,13 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
 /* Queue one solve: parameters, mesh, initial state (host [5][E][(N+1)^3]),
  * n_steps of size dt.  dt < 0 asks for the stable step of dg_stable_dt with
  * CFL = DFL = -dt on the initial state, evaluated in FP64 on the host when
- * the request is prepared.  All host data is copied.  Once a request has
- * arrived, a thread of the server builds its geometry and metrics while the
- * serving loop runs; a mesh that fails those checks ends DG_REQ_FAILED.  t_arrival: the caller's clock, seconds since server
- * creation; the request becomes eligible for admission once the server clock
- * passes it.  DG_EBUSY if it can never fit the budget. */
+ * the request is prepared.  All host data is copied.  t_arrival: the caller's
+ * clock, seconds since server creation; the request becomes eligible for
+ * admission once the server clock passes it.  Once a request has arrived, a
+ * thread of the server builds its geometry and metrics while the serving loop
+ * runs, reusing those of an identical mesh and set-up seen before (up to
+ * 4 GiB of them are kept in host memory); a mesh that fails those checks ends
+ * DG_REQ_FAILED.  DG_EBUSY if it can never fit the budget. */
 dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, const double *U0_host,
                            int32_t n_steps, double dt, double t_arrival, int64_t *req_id);
 

@@ -40,6 +40,8 @@ struct View {
   real *alpha;      // [E] blending factors
   real *alpha_raw;  // [E] indicator values before neighbour propagation
   const real *alpha_in; // [E] frozen blending factors or null
+  char *base;       // batched launches, in the argument view: the arena that the
+                    // descriptors' pointer fields are byte offsets into
   real gamma, Rgas, rRgas, mu, lambda; // perfect gas (rRgas = 1/R), constant viscosity and conductivity
   double Pr;        // Prandtl number (time-step estimate only)
   double t, dt, rkA, rkB;       // stage time, step, LSERK coefficients

@@ -84,8 +84,10 @@ __device__ __forceinline__ void prolong_state(const real *rows, const real *lv, 
 }
 
 // which view and which element block this workgroup works on: a single
-// solve takes its view from the kernel arguments; a batch of solves looks its
-// request up in the block prefix sums and loads that request's view.
+// solve (nreq = 0) takes its view from the kernel arguments; a batch of solves
+// looks its request up in the block prefix sums and loads that request's view.
+// One instantiation serves both, so a request computes the same bits alone and
+// in any batch.
 // The hardware hands consecutive workgroups to the eight XCDs in turn; with
 // `remap` each XCD instead receives one contiguous range of element blocks, so
 // face neighbours (adjacent element indices) share that XCD's L2.  A bijection
@@ -96,10 +98,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return start + idx;
 }
 
-template <bool BATCH, typename real>
+template <typename real>
 __device__ __forceinline__ View<real> select_view(const View<real> *views, const int *blk_start, int nreq,
                                                   const View<real> &single, int &lblk) {
-  if (!BATCH) {
+  if (nreq == 0) {
     lblk = single.remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     return single;
   }
@@ -107,7 +109,30 @@ __device__ __forceinline__ View<real> select_view(const View<real> *views, const
   int r = 0;
   while (r + 1 < nreq && b >= blk_start[r + 1]) ++r;
   lblk = b - blk_start[r];
-  return views[r];
+  // the descriptors hold byte offsets into the arena; rebuilding the pointers
+  // from the argument's arena pointer keeps every access a global-memory one
+  // (pointers read from memory would be addressed as generic pointers)
+  View<real> v = views[r];
+  char *const base = single.base;
+  auto at = [base](auto p) { return (decltype(p))(base + (intptr_t)p); };
+  auto at_or_null = [base](auto p) { return p ? (decltype(p))(base + (intptr_t)p) : p; };
+  v.U = at(v.U);
+  v.dU = at(v.dU);
+  v.R = at_or_null(v.R);
+  v.Ja = at(v.Ja);
+  v.invJ = at(v.invJ);
+  v.NS = at(v.NS);
+  v.Utr0 = at(v.Utr0);
+  v.Utr1 = at(v.Utr1);
+  v.Hv = at_or_null(v.Hv);
+  v.Vol = at_or_null(v.Vol);
+  v.conn = at(v.conn);
+  v.Xs = at_or_null(v.Xs);
+  v.basis = at(v.basis);
+  v.alpha = at(v.alpha);
+  v.alpha_raw = at(v.alpha_raw);
+  v.alpha_in = at_or_null(v.alpha_in);
+  return v;
 }
 
 template <int N, typename real>
@@ -134,13 +159,13 @@ __device__ __forceinline__ void load_basis(Smem<N, real> &sb, const real *basis)
 // ---------------------------------------------------------------------------
 // ProlongToFace of the state into the current trace buffer
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH>
+template <int N, typename real>
 __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *views, const int *blk_start, int nreq,
                                                          View<real> single) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
   int lblk;
-  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
+  const View<real> v = select_view(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
   __shared__ real sU[epb][5 * Pad<n>::size];
   load_basis<N, real>(sb, v.basis);
@@ -255,13 +280,13 @@ __device__ __forceinline__ void prim2cons(const real *q, real gamma, real *U) {
 // direction at a time, the SurfInt gather, ApplyJac, the stage update and the
 // next U traces.  mode 0: du = A du + dt R, U += B du; mode 1: write R only.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH>
+template <int N, typename real>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<real> *views, const int *blk_start,
                                                                       int nreq, View<real> single, int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
   int lblk;
-  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
+  const View<real> v = select_view(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
   // contravariant fluxes of one direction (rows of n3), later the updated
   // state (padded rows) for the next traces
@@ -526,14 +551,14 @@ struct VolLds {
 // the mass component is zero) and the volume integral (5 per node); with
 // shock capturing also the element's indicator value.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH, bool SHOCK>
+template <int N, typename real, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const View<real> *views, const int *blk_start,
                                                                          int nreq, View<real> single) {
   using S = Sz<N>;
   using L = VolLds<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
   int lblk;
-  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
+  const View<real> v = select_view(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
   __shared__ real sA[epb][L::rows];
   load_basis<N, real>(sb, v.basis);
@@ -786,13 +811,13 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
 // the blend of the FV subcell operator; SurfInt gather, ApplyJac, the stage
 // update (mode 0) or R (mode 1), and the next U traces.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool BATCH, bool SHOCK>
+template <int N, typename real, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
                                                                           int nreq, View<real> single, int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
   int lblk;
-  const View<real> v = select_view<BATCH>(views, blk_start, nreq, single, lblk);
+  const View<real> v = select_view(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
   __shared__ real sB[epb][5][Pad<n>::size];
   __shared__ real sS[epb][5][nf];
@@ -1161,41 +1186,34 @@ template <int N, typename real>
 static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const int *blk_start, int nreq, int blocks,
                            const View<real> &v0, hipStream_t st) {
   dim3 grid(blocks), block(Sz<N>::threads);
-  const bool batch = nreq > 0;
   switch (k) {
     case K_TRACE:
-      if (batch) k_trace<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-      else k_trace<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+      k_trace<N, real><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       break;
     case K_LIFT:
       // volume sweep: indicator (shock capturing), lifting (viscous), VolInt
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          if (batch) k_volume<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-          else k_volume<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+          k_volume<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
         } else {
           return hipErrorInvalidValue;
         }
       } else {
-        if (batch) k_volume<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
-        else k_volume<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        k_volume<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       }
       break;
     case K_RHS:
       // surface sweep (after a volume sweep), or the one-sweep Euler operator
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          if (batch) k_surface<N, real, true, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-          else k_surface<N, real, false, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          k_surface<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
         } else {
           return hipErrorInvalidValue;
         }
       } else if (v0.viscous) {
-        if (batch) k_surface<N, real, true, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-        else k_surface<N, real, false, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        k_surface<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       } else {
-        if (batch) k_rhs<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-        else k_rhs<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        k_rhs<N, real><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       }
       break;
     default: return hipErrorInvalidValue;

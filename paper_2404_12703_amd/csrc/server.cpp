@@ -1,7 +1,10 @@
 // server.cpp -- continuous batching of many independent DGSEM solves on one GPU.
 //
-// Requests are queued with their parameters, mesh and initial state.  Each
-// call of the loop (dg_server_run) repeats: admit queued requests in arrival
+// Requests are queued with their parameters, mesh and initial state.  A
+// preparation thread builds the host set-up (geometry, metrics, the CFL step)
+// of each request once it has arrived, reusing the set-up of an identical mesh
+// seen before.  Each call of the loop (dg_server_run) repeats: admit prepared
+// requests in arrival
 // order while the memory budget and the slot table allow (strict FIFO: the
 // head of the queue is never overtaken); run one RK stage for every active
 // request -- one launch per kernel for every group of requests sharing
@@ -37,6 +40,7 @@ namespace {
 
 constexpr int kDescSlots = 16;  // ring of descriptor uploads in flight
 constexpr int kPrepAhead = 16;  // requests at the head of the queue prepared ahead of admission
+constexpr size_t kGeoCacheBytes = size_t(4) << 30;  // host memory of the geometry cache
 enum { PREP_WAITING = 0, PREP_RUNNING = 1, PREP_READY = 2, PREP_FAILED = 3 };
 
 struct Request {
@@ -62,7 +66,7 @@ struct Request {
   bool traces_valid = false;
   // host set-up, made by the preparation thread once the request has arrived;
   // kept until its upload has landed
-  std::unique_ptr<HostSetup> host;
+  std::shared_ptr<const HostSetup> host;
   std::atomic<int> prep{PREP_WAITING};
   std::string prep_err;
   hipEvent_t ready = nullptr;  // set-up copies done
@@ -72,6 +76,85 @@ struct Request {
   int *flag_host = nullptr;
   hipEvent_t done_ev = nullptr;
   bool retiring = false;
+};
+
+// Set-ups of meshes seen before, kept by the preparation thread (the only
+// user).  A hit needs the same parameters that shape the set-up and a mesh
+// equal byte for byte to the stored copy; least recently used entries go
+// beyond kGeoCacheBytes.
+struct GeoCache {
+  struct Entry {
+    std::shared_ptr<const HostSetup> hs;
+    dg_params p{};
+    int n_geo = 0;
+    std::vector<double> x_geo;
+    std::vector<int64_t> nbr_elem;
+    std::vector<int8_t> nbr_face, nbr_orient;
+    size_t bytes = 0;
+    uint64_t used = 0;
+  };
+  std::multimap<uint64_t, Entry> map;  // content hash -> entries
+  size_t bytes = 0;
+  uint64_t clock = 0;
+
+  static uint64_t mix(uint64_t h, const void *data, size_t n) {
+    const unsigned char *c = (const unsigned char *)data;
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, c + i, 8);
+      h = (h ^ w) * 0x100000001b3ULL;
+      h ^= h >> 29;
+    }
+    for (; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ULL;
+    return h;
+  }
+  static uint64_t key(const Request &r) {
+    uint64_t h = 0xcbf29ce484222325ULL;
+    const int32_t shape[6] = {r.p.N, r.p.nodes, r.p.precision, r.p.source, r.n_geo, 0};
+    h = mix(h, shape, sizeof shape);
+    h = mix(h, &r.E, sizeof r.E);
+    h = mix(h, r.x_geo.data(), r.x_geo.size() * 8);
+    h = mix(h, r.nbr_elem.data(), r.nbr_elem.size() * 8);
+    h = mix(h, r.nbr_face.data(), r.nbr_face.size());
+    return mix(h, r.nbr_orient.data(), r.nbr_orient.size());
+  }
+  static bool same(const Entry &en, const Request &r) {
+    return en.p.N == r.p.N && en.p.nodes == r.p.nodes && en.p.precision == r.p.precision &&
+           en.p.source == r.p.source && en.n_geo == r.n_geo && en.x_geo == r.x_geo && en.nbr_elem == r.nbr_elem &&
+           en.nbr_face == r.nbr_face && en.nbr_orient == r.nbr_orient;
+  }
+  std::shared_ptr<const HostSetup> find(uint64_t k, const Request &r) {
+    auto range = map.equal_range(k);
+    for (auto it = range.first; it != range.second; ++it)
+      if (same(it->second, r)) {
+        it->second.used = ++clock;
+        return it->second.hs;
+      }
+    return nullptr;
+  }
+  void insert(uint64_t k, const Request &r, std::shared_ptr<const HostSetup> hs) {
+    Entry en;
+    en.hs = std::move(hs);
+    en.p = r.p;
+    en.n_geo = r.n_geo;
+    en.x_geo = r.x_geo;
+    en.nbr_elem = r.nbr_elem;
+    en.nbr_face = r.nbr_face;
+    en.nbr_orient = r.nbr_orient;
+    en.bytes = en.hs->bytes() + 8 * (en.x_geo.size() + en.nbr_elem.size()) + 2 * en.nbr_face.size();
+    if (en.bytes > kGeoCacheBytes) return;
+    while (bytes + en.bytes > kGeoCacheBytes && !map.empty()) {
+      auto lru = map.begin();
+      for (auto it = map.begin(); it != map.end(); ++it)
+        if (it->second.used < lru->second.used) lru = it;
+      bytes -= lru->second.bytes;
+      map.erase(lru);
+    }
+    en.used = ++clock;
+    bytes += en.bytes;
+    map.emplace(k, std::move(en));
+  }
 };
 
 // first-fit allocator over [0, budget) of the arena, 256-byte granules
@@ -135,6 +218,7 @@ struct dg_server {
   std::condition_variable prep_cv;
   bool prep_stop = false;
   std::thread prep_thread;
+  GeoCache geo;  // the preparation thread's
   std::vector<int64_t> active;
   int64_t next_id = 1;
   std::chrono::steady_clock::time_point t0;
@@ -179,14 +263,25 @@ void prep_loop(dg_server *sv) {
     }
     next->prep.store(PREP_RUNNING, std::memory_order_relaxed);
     lk.unlock();
-    std::unique_ptr<HostSetup> hs(new HostSetup());
-    dg_mesh m{next->E, next->n_geo, 0, next->x_geo.data(), next->nbr_elem.data(), next->nbr_face.data(),
-              next->nbr_orient.data()};
+    const uint64_t k = GeoCache::key(*next);
+    std::shared_ptr<const HostSetup> hs = sv->geo.find(k, *next);
+    dg_status rc = DG_OK;
     std::string err;
-    const dg_status rc = setup_host(next->p, m, next->U0.data(), next->dt < 0.0 ? -next->dt : 0.0, *hs, err);
+    if (!hs) {
+      std::shared_ptr<HostSetup> fresh(new HostSetup());
+      dg_mesh m{next->E, next->n_geo, 0, next->x_geo.data(), next->nbr_elem.data(), next->nbr_face.data(),
+                next->nbr_orient.data()};
+      rc = setup_host(next->p, m, *fresh, err);
+      if (rc == DG_OK) {
+        sv->geo.insert(k, *next, fresh);
+        hs = std::move(fresh);
+      }
+    }
+    double dt = next->dt;
+    if (rc == DG_OK && dt < 0.0) dt = host_stable_dt(next->p, next->E, *hs, next->U0.data(), -dt);
     lk.lock();
     if (rc == DG_OK) {
-      if (next->dt < 0.0) next->dt = hs->dt;
+      next->dt = dt;
       next->host = std::move(hs);
       next->prep.store(PREP_READY, std::memory_order_release);
     } else {
@@ -262,6 +357,30 @@ View<float> &view_of<float>(Request &r) {
   return r.vf;
 }
 
+// a view with its pointers turned into byte offsets from the arena (the form
+// the batched kernels read; null stays null)
+template <typename real>
+View<real> as_offsets(View<real> v, const char *arena) {
+  auto off = [arena](auto p) { return p ? (decltype(p))(intptr_t)((const char *)p - arena) : p; };
+  v.U = off(v.U);
+  v.dU = off(v.dU);
+  v.R = off(v.R);
+  v.Ja = off(v.Ja);
+  v.invJ = off(v.invJ);
+  v.NS = off(v.NS);
+  v.Utr0 = off(v.Utr0);
+  v.Utr1 = off(v.Utr1);
+  v.Hv = off(v.Hv);
+  v.Vol = off(v.Vol);
+  v.conn = off(v.conn);
+  v.Xs = off(v.Xs);
+  v.basis = off(v.basis);
+  v.alpha = off(v.alpha);
+  v.alpha_raw = off(v.alpha_raw);
+  v.alpha_in = off(v.alpha_in);
+  return v;
+}
+
 // one batched launch of kernel k over the group; descriptors go through the ring
 template <typename real>
 dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request *> &grp) {
@@ -283,7 +402,7 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
     v.rkB = RK_B[q.stage];
     v.cur = q.cur;
     v.R = nullptr;
-    views[r] = v;
+    views[r] = as_offsets(v, sv->arena);
     blk[r] = total;
     total += blocks_per_elements(N, q.E);
   }
@@ -291,9 +410,12 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
   char *d = sv->arena + slot * sv->desc_stride;
   e = hipMemcpyAsync(d, h, sv->desc_stride, hipMemcpyHostToDevice, sv->st);
   if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[slot], sv->st);
+  // the argument view: the group's settings (shock capturing, viscosity) and the arena
+  View<real> v0 = view_of<real>(*grp[0]);
+  v0.base = sv->arena;
   if (e == hipSuccess)
     e = launch<real>(k, N, 0, (const View<real> *)d, (const int *)(d + sv->max_active * view_bytes()), (int)grp.size(),
-                     total, views[0], sv->st);
+                     total, v0, sv->st);
   if (e != hipSuccess) return server_fail(sv, e, "batched launch");
   return DG_OK;
 }

@@ -113,6 +113,7 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.alpha = (real *)at(L.alpha);
   v.alpha_raw = (real *)at(L.alpha_raw);
   v.alpha_in = nullptr;
+  v.base = nullptr;
   v.gamma = (real)p.gamma;
   v.Rgas = (real)p.R;
   v.rRgas = (real)(1.0 / p.R);
@@ -143,44 +144,13 @@ template void fill_view<double>(View<double> &, void *, const Layout &, const dg
 template void fill_view<float>(View<float> &, void *, const Layout &, const dg_params &, int64_t);
 
 // Host set-up of one solve (no HIP calls), then its upload.
-dg_status setup_host(const dg_params &p, const dg_mesh &m, const double *U0, double cfl, HostSetup &hs,
-                     std::string &err) {
+dg_status setup_host(const dg_params &p, const dg_mesh &m, HostSetup &hs, std::string &err) {
   Basis b = make_basis(p.N, p.nodes);
   Geometry g;
   dg_status rc = build_geometry(b, m, g, err);
   if (rc) return rc;
-  const int64_t E = m.n_elems;
-  const int n = p.N + 1, n3 = n * n * n;
   std::vector<double> invJ(g.J.size());
   for (size_t i = 0; i < g.J.size(); ++i) invJ[i] = 1.0 / g.J[i];
-  if (U0 && cfl > 0.0) {
-    // the time-step estimate of dg_stable_dt (App. A.5): convective
-    // 2/((2N+1) sum_i lambda_i) and, with viscosity, 4/((N+1)^4 nu sum_i (|Ja^i|/J)^2)
-    const double gam = p.gamma, nfac = std::pow((double)n, 4.0);
-    double dta = 1e300, dtv = 1e300;
-    for (int64_t e = 0; e < E; ++e)
-      for (int a = 0; a < n3; ++a) {
-        double U[5];
-        for (int c = 0; c < 5; ++c) U[c] = U0[((size_t)c * E + e) * n3 + a];
-        const double rho = U[0], ir = 1.0 / rho, u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
-        const double pr = (gam - 1.0) * (U[4] - 0.5 * rho * (u * u + v * v + w * w));
-        const double c = std::sqrt(gam * pr / rho), iJ = invJ[(size_t)e * n3 + a];
-        double lamsum = 0.0, vis = 0.0;
-        for (int ci = 0; ci < 3; ++ci) {
-          const double j0 = g.Ja[((size_t)(3 * ci) * E + e) * n3 + a], j1 = g.Ja[((size_t)(3 * ci + 1) * E + e) * n3 + a],
-                       j2 = g.Ja[((size_t)(3 * ci + 2) * E + e) * n3 + a];
-          const double nj = std::sqrt(j0 * j0 + j1 * j1 + j2 * j2);
-          lamsum += (std::fabs(u * j0 + v * j1 + w * j2) + c * nj) * iJ;
-          vis += (nj * iJ) * (nj * iJ);
-        }
-        dta = std::min(dta, 2.0 / ((2.0 * p.N + 1.0) * lamsum));
-        if (p.viscous && p.mu > 0) {
-          const double nu = std::max(4.0 / 3.0, gam / p.Pr) * p.mu / rho;
-          dtv = std::min(dtv, 4.0 / (nfac * nu * vis));
-        }
-      }
-    hs.dt = std::min(cfl * dta, cfl * dtv);
-  }
   std::vector<double> blk = basis_block(b);
   if (p.precision == 1) {
     auto to_f = [](const std::vector<double> &x) {
@@ -201,6 +171,39 @@ dg_status setup_host(const dg_params &p, const dg_mesh &m, const double *U0, dou
   hs.conn = std::move(g.conn);
   if (p.source) hs.Xs = std::move(g.Xs);
   return DG_OK;
+}
+
+double host_stable_dt(const dg_params &p, int64_t E, const HostSetup &hs, const double *U0, double cfl) {
+  // the time-step estimate of dg_stable_dt (App. A.5): convective
+  // 2/((2N+1) sum_i lambda_i) and, with viscosity, 4/((N+1)^4 nu sum_i (|Ja^i|/J)^2)
+  const int n = p.N + 1, n3 = n * n * n;
+  const bool mixed = p.precision == 1;
+  auto ja = [&](size_t i) { return mixed ? (double)hs.fJa[i] : hs.Ja[i]; };
+  auto ij = [&](size_t i) { return mixed ? (double)hs.finvJ[i] : hs.invJ[i]; };
+  const double gam = p.gamma, nfac = std::pow((double)n, 4.0);
+  double dta = 1e300, dtv = 1e300;
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < n3; ++a) {
+      double U[5];
+      for (int c = 0; c < 5; ++c) U[c] = U0[((size_t)c * E + e) * n3 + a];
+      const double rho = U[0], ir = 1.0 / rho, u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
+      const double pr = (gam - 1.0) * (U[4] - 0.5 * rho * (u * u + v * v + w * w));
+      const double c = std::sqrt(gam * pr / rho), iJ = ij((size_t)e * n3 + a);
+      double lamsum = 0.0, vis = 0.0;
+      for (int ci = 0; ci < 3; ++ci) {
+        const double j0 = ja(((size_t)(3 * ci) * E + e) * n3 + a), j1 = ja(((size_t)(3 * ci + 1) * E + e) * n3 + a),
+                     j2 = ja(((size_t)(3 * ci + 2) * E + e) * n3 + a);
+        const double nj = std::sqrt(j0 * j0 + j1 * j1 + j2 * j2);
+        lamsum += (std::fabs(u * j0 + v * j1 + w * j2) + c * nj) * iJ;
+        vis += (nj * iJ) * (nj * iJ);
+      }
+      dta = std::min(dta, 2.0 / ((2.0 * p.N + 1.0) * lamsum));
+      if (p.viscous && p.mu > 0) {
+        const double nu = std::max(4.0 / 3.0, gam / p.Pr) * p.mu / rho;
+        dtv = std::min(dtv, 4.0 / (nfac * nu * vis));
+      }
+    }
+  return std::min(cfl * dta, cfl * dtv);
 }
 
 hipError_t setup_device(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st) {
@@ -357,7 +360,7 @@ dg_status dg_create(const dg_params *p, const dg_mesh *m, void *d_workspace, siz
   fill_view(s->vf, s->ws, L, *p, s->E);
   HostSetup hs;
   std::string err;
-  rc = setup_host(*p, *m, nullptr, 0.0, hs, err);
+  rc = setup_host(*p, *m, hs, err);
   if (rc) return fail(rc, err);
   hipError_t e = setup_device(*p, hs, s->ws, L, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);  // the host buffers go out of scope

@@ -29,21 +29,26 @@ dg_status fail(dg_status code, const std::string &msg);
 extern const double RK_A[5], RK_B[5], RK_C[5];
 
 // Host half of a solve's set-up: bases, geometry and metrics in the solve's
-// arithmetic type, ready to upload, and (when asked) the stable step on the
-// initial state.  Makes no HIP call, so it may run on any thread.
+// arithmetic type, ready to upload.  Makes no HIP call, so it may run on any
+// thread.
 struct HostSetup {
   std::vector<double> Ja, invJ, NS, basis, Xs;  // FP64 form
   std::vector<float> fJa, finvJ, fNS, fbasis;   // mixed form
   std::vector<int2> conn;
-  double dt = 0.0;
+  size_t bytes() const {
+    return 8 * (Ja.size() + invJ.size() + NS.size() + basis.size() + Xs.size()) +
+           4 * (fJa.size() + finvJ.size() + fNS.size() + fbasis.size()) + sizeof(int2) * conn.size();
+  }
 };
 
 template <typename real>
 void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, int64_t E);
-// U0 [5][E][n3] and cfl > 0: also dt = the step of dg_stable_dt with CFL =
-// DFL = cfl, in FP64 from the FP64 metrics.  DG_EMESH with err on a bad mesh.
-dg_status setup_host(const dg_params &p, const dg_mesh &m, const double *U0, double cfl, HostSetup &hs,
-                     std::string &err);
+// DG_EMESH with err on a mesh that fails the geometric checks
+dg_status setup_host(const dg_params &p, const dg_mesh &m, HostSetup &hs, std::string &err);
+// the step of dg_stable_dt with CFL = DFL = cfl on the state U0 [5][E][n3],
+// in FP64 from the set-up's metrics (in the solve's arithmetic type, as on
+// the device)
+double host_stable_dt(const dg_params &p, int64_t E, const HostSetup &hs, const double *U0, double cfl);
 // zero the workspace and copy the set-up in on st; hs must stay alive until
 // the copies have completed
 hipError_t setup_device(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st);
