@@ -528,7 +528,20 @@ __device__ __forceinline__ void fv_subcells(real *rows, const real *sFV, bool ac
   }
 }
 
-template <int N>
+// Face work unit t of an element: the direction d and first side s0 of its
+// face nodes and their face index pq.  fpu = 2: both sides of line pq; fpu = 1:
+// face node t.  With plane waves each wave's units share one face direction.
+template <int n, int fpu, bool plane_waves>
+__device__ __forceinline__ void face_unit(int t, int &d, int &s0, int &pq) {
+  constexpr int n2 = n * n;
+  int g = t / n2;  // d (fpu = 2) or the face (fpu = 1)
+  if constexpr (plane_waves) g = __builtin_amdgcn_readfirstlane(g);
+  pq = t - g * n2;
+  d = fpu == 2 ? g : g >> 1;
+  s0 = fpu == 2 ? 0 : g & 1;
+}
+
+template <int N, typename real, bool SHOCK>
 struct VolLds {
   using S = Sz<N>;
   static constexpr int n3 = S::n3, nf = S::nf;
@@ -539,7 +552,18 @@ struct VolLds {
   static constexpr int V = 0, J = 4 * n3, Avg = 13 * n3, Ns = Avg + 4 * nf, G = 0, F = 0;
   static constexpr int gsz = Pad<S::n>::size;  // one padded row of g
   static constexpr int rows = (Ns + 3 * nf) > 15 * n3 ? (Ns + 3 * nf) : 15 * n3;
-  static constexpr int fpt = (nf + n3 - 1) / n3;  // face nodes per thread
+  // Face work units: with fpu = 2 a thread takes the two face nodes at the
+  // ends of one line of nodes, so the line of g is read once for both; with
+  // fpu = 1 one face node.  Two per unit halves the LDS reads of
+  // Lift_ProlongToFace but also the threads that share them.  Measured per
+  // degree on ~7M-DOF meshes, one per unit is faster at N = 6, and at N = 5
+  // in FP64; two elsewhere (8% less volume-sweep time at N = 3, 3% at N = 7).
+  // The FP64 sweeps at N = 9 and with shock capturing at N = 7 take one: two
+  // would spill registers.
+  static constexpr bool f64 = sizeof(real) == 8;
+  static constexpr int fpu = (N == 6 || (f64 && (N == 5 || N >= 9 || (N == 7 && SHOCK)))) ? 1 : 2;
+  static constexpr int units = nf / fpu;
+  static constexpr int upt = (units + n3 - 1) / n3;  // units per thread
   static_assert(12 * gsz <= Ns, "g must not cover n shat");
 };
 
@@ -555,7 +579,7 @@ template <int N, typename real, bool SHOCK>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const View<real> *views, const int *blk_start,
                                                                          int nreq, View<real> single) {
   using S = Sz<N>;
-  using L = VolLds<N>;
+  using L = VolLds<N, real, SHOCK>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
   int lblk;
   const View<real> v = select_view(views, blk_start, nreq, single, lblk);
@@ -586,7 +610,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     for (int al = 0; al < n; ++al) dk[al] = v.basis[o.Dhat + ku * n + al];
   }
   real U[5];
-  real pf[L::fpt][3];  // own face velocity at this thread's face nodes
+  real pf[L::upt][L::fpu][3];  // own face velocity at this thread's face nodes
   if (active) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = (real)(v.U + c * Ev)[vi];
@@ -622,31 +646,35 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     // Lift_FillFlux: the BR1 average of both sides' traces, and this side's
     // outward n shat and face velocity for its viscous flux later on
 #pragma unroll
-    for (int r = 0; r < L::fpt; ++r) {
-      const int fn = a + r * n3;
-      if (fn < nf) {
-        int f = fn / n2;
-        if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
-        const int pq = fn - f * n2, p = pq % n, q = pq / n;
-        const int2 c = v.conn[e * 6 + f];
-        int pp, qq;
-        orient_map(c.y & 7, p, q, N, pp, qq);
-        const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
-        real Uo[5], Un[5], Po[6], Pn[6];
+    for (int r = 0; r < L::upt; ++r) {
+      const int t = a + r * n3;
+      if (t < L::units) {
+        int d, s0, pq;
+        face_unit<n, L::fpu, plane_waves>(t, d, s0, pq);
+        const int p = pq % n, q = pq / n;
 #pragma unroll
-        for (int s = 0; s < 5; ++s) {
-          Uo[s] = (tr + s * Ef)[io];
-          Un[s] = (tr + s * Ef)[in];
-        }
-        cons2prim(Uo, gam, rR, Po);
-        cons2prim(Un, gam, rR, Pn);
-        const real vo[4] = {Po[1], Po[2], Po[3], Po[5]}, vn[4] = {Pn[1], Pn[2], Pn[3], Pn[5]};
+        for (int u = 0; u < L::fpu; ++u) {
+          const int f = 2 * d + s0 + u, fn = f * n2 + pq;
+          const int2 c = v.conn[e * 6 + f];
+          int pp, qq;
+          orient_map(c.y & 7, p, q, N, pp, qq);
+          const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
+          real Uo[5], Un[5], Po[6], Pn[6];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) sm[L::Avg + s * nf + fn] = real(0.5) * (vo[s] + vn[s]);
+          for (int s = 0; s < 5; ++s) {
+            Uo[s] = (tr + s * Ef)[io];
+            Un[s] = (tr + s * Ef)[in];
+          }
+          cons2prim(Uo, gam, rR, Po);
+          cons2prim(Un, gam, rR, Pn);
+          const real vo[4] = {Po[1], Po[2], Po[3], Po[5]}, vn[4] = {Pn[1], Pn[2], Pn[3], Pn[5]};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          sm[L::Ns + d * nf + fn] = (v.NS + d * Ef)[io];
-          pf[r][d] = Po[1 + d];
+          for (int s = 0; s < 4; ++s) sm[L::Avg + s * nf + fn] = real(0.5) * (vo[s] + vn[s]);
+#pragma unroll
+          for (int dd = 0; dd < 3; ++dd) {
+            sm[L::Ns + dd * nf + fn] = (v.NS + dd * Ef)[io];
+            pf[r][u][dd] = Po[1 + dd];
+          }
         }
       }
     }
@@ -736,47 +764,66 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   if (active && visc) {
     // Lift_ProlongToFace of g, then this side's viscous normal flux
 #pragma unroll
-    for (int r = 0; r < L::fpt; ++r) {
-      const int fn = a + r * n3;
-      if (fn < nf) {
-        int f = fn / n2;
-        if constexpr (plane_waves) f = __builtin_amdgcn_readfirstlane(f);
-        const int pq = fn - f * n2;
+    for (int r = 0; r < L::upt; ++r) {
+      const int t = a + r * n3;
+      if (t < L::units) {
+        int d, s0, pq;
+        face_unit<n, L::fpu, plane_waves>(t, d, s0, pq);
         int base, stride;
-        Pad<n>::face_line(f, pq, base, stride);
-        const real *lv = (f & 1) ? sb.lp : sb.lm;
-        real gt[12];
+        Pad<n>::face_line(2 * d, pq, base, stride);
+        // l(-1) and l(+1) weights: scalar loads where the face is the same on
+        // every lane
+        const BasisOffsets o(n);
+        const real *lw[L::fpu];
 #pragma unroll
-        for (int s = 0; s < 12; ++s) gt[s] = real(0);
+        for (int u = 0; u < L::fpu; ++u) {
+          const bool plus = (s0 + u) != 0;
+          lw[u] = plane_waves ? v.basis + (plus ? o.lp : o.lm) : (plus ? sb.lp : sb.lm);
+        }
+        real gt[L::fpu][12];
+#pragma unroll
+        for (int u = 0; u < L::fpu; ++u)
+#pragma unroll
+          for (int s = 0; s < 12; ++s) gt[u][s] = real(0);
 #pragma unroll
         for (int l = 0; l < n; ++l) {
-          const real lw = lv[l];
+          real w[L::fpu];
+#pragma unroll
+          for (int u = 0; u < L::fpu; ++u) w[u] = lw[u][l];
           const real *row = sm + L::G + base + l * stride;
 #pragma unroll
-          for (int s = 0; s < 12; ++s) gt[s] += lw * row[s * L::gsz];
+          for (int s = 0; s < 12; ++s) {
+            const real gv = row[s * L::gsz];
+#pragma unroll
+            for (int u = 0; u < L::fpu; ++u) gt[u][s] += w[u] * gv;
+          }
         }
-        const bool primary = (v.conn[e * 6 + f].y >> 3) & 1;
-        real nsv[3];
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-          const real ns = sm[L::Ns + dd * nf + fn];
-          nsv[dd] = primary ? ns : -ns;
+        for (int u = 0; u < L::fpu; ++u) {
+          const int f = 2 * d + s0 + u, fn = f * n2 + pq;
+          const bool primary = (v.conn[e * 6 + f].y >> 3) & 1;
+          real nsv[3];
+#pragma unroll
+          for (int dd = 0; dd < 3; ++dd) {
+            const real ns = sm[L::Ns + dd * nf + fn];
+            nsv[dd] = primary ? ns : -ns;
+          }
+          const real ish = real(1) / sqrt(nsv[0] * nsv[0] + nsv[1] * nsv[1] + nsv[2] * nsv[2]);
+          const real nv[3] = {nsv[0] * ish, nsv[1] * ish, nsv[2] * ish};
+          const real Pf[6] = {real(0), pf[r][u][0], pf[r][u][1], pf[r][u][2], real(0), real(0)};
+          real H[5] = {0, 0, 0, 0, 0}, tmp[5];
+          flux_visc<0>(Pf, gt[u], mu, lam, tmp);
+#pragma unroll
+          for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[0];
+          flux_visc<1>(Pf, gt[u], mu, lam, tmp);
+#pragma unroll
+          for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[1];
+          flux_visc<2>(Pf, gt[u], mu, lam, tmp);
+#pragma unroll
+          for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[2];
+#pragma unroll
+          for (int s = 1; s < 5; ++s) (v.Hv + (s - 1) * Ef)[fb + fn] = H[s];
         }
-        const real ish = real(1) / sqrt(nsv[0] * nsv[0] + nsv[1] * nsv[1] + nsv[2] * nsv[2]);
-        const real nv[3] = {nsv[0] * ish, nsv[1] * ish, nsv[2] * ish};
-        const real Pf[6] = {real(0), pf[r][0], pf[r][1], pf[r][2], real(0), real(0)};
-        real H[5] = {0, 0, 0, 0, 0}, tmp[5];
-        flux_visc<0>(Pf, gt, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[0];
-        flux_visc<1>(Pf, gt, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[1];
-        flux_visc<2>(Pf, gt, mu, lam, tmp);
-#pragma unroll
-        for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[2];
-#pragma unroll
-        for (int s = 1; s < 5; ++s) (v.Hv + (s - 1) * Ef)[fb + fn] = H[s];
       }
     }
   }
@@ -849,13 +896,19 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
   const int i = a % n, j = (a / n) % n, k = a / n2;
   constexpr bool plane_waves = n2 == 64 && epb == 1;  // a wave is one face of one element
   real *const su = &sB[le < epb ? le : 0][0][0];
-  // the state, in registers for the update and in LDS for this element's own traces
+  const int pa = Pad<n>::at(i, j, k);
+  // the state, in LDS for this element's own traces and for the update.  The
+  // FP64 copy is exact, so it is read back after the face phase instead of
+  // being held in registers through it (they would spill); the mixed form
+  // keeps the FP64 values, and so does the shock-capturing sweep, whose
+  // occupancy its LDS sets.
+  constexpr bool exact_lds = sizeof(real) == sizeof(double) && !SHOCK;
   double Uold[5] = {0, 0, 0, 0, 0};
   if (active) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       Uold[c] = (v.U + c * Ev)[vi];
-      su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Uold[c];
+      su[c * Pad<n>::size + pa] = (real)Uold[c];
     }
     if (SHOCK && a == 0) {
       // blending factor: frozen, or the element's indicator value raised to
@@ -931,6 +984,12 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
     }
   }
   __syncthreads();
+  if constexpr (exact_lds) {
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Uold[c] = su[c * Pad<n>::size + pa];
+    }
+  }
   // blended elements: alpha (V_FV - V_adv) joins the stored volume integral,
   // i.e. (1 - alpha) V_adv + alpha V_FV + V_visc
   real Vb[5] = {0, 0, 0, 0, 0};
@@ -1026,7 +1085,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
     // (every face-phase read of the old state is behind the barrier above)
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Unew[c];
+      for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + pa] = (real)Unew[c];
     }
     __syncthreads();
     if (active) {
