@@ -562,9 +562,22 @@ struct VolLds {
   // would spill registers.
   static constexpr bool f64 = sizeof(real) == 8;
   static constexpr int fpu = (N == 6 || (f64 && (N == 5 || N >= 9 || (N == 7 && SHOCK)))) ? 1 : 2;
+  // Nodes per thread: where a wave is one k-plane of one element (N = 7),
+  // a thread of the mixed form without shock capturing takes the two nodes k
+  // and k + n/2 of one column.  They share the reads along zeta, the D-hat
+  // rows along xi and eta and the zeta faces of Lift_SurfInt; the workgroup
+  // has half the threads, each with twice the registers.  That took 7% off
+  // the mixed sweep; in FP64 the pairs need all 256 VGPRs at two waves per
+  // SIMD and measured no faster.
+  static constexpr bool plane_waves = S::n2 == 64 && S::epb == 1;
+  static constexpr int npt = (plane_waves && !SHOCK && !f64) ? 2 : 1;
+  static constexpr int tpe = n3 / npt;  // threads per element
+  static constexpr int threads = npt == 1 ? S::threads : tpe;
+  static constexpr int minw = npt == 1 ? S::minw : 2;
   static constexpr int units = nf / fpu;
-  static constexpr int upt = (units + n3 - 1) / n3;  // units per thread
+  static constexpr int upt = (units + tpe - 1) / tpe;  // units per thread
   static_assert(12 * gsz <= Ns, "g must not cover n shat");
+  static_assert(npt == 1 || (S::n % 2 == 0 && S::epb == 1), "column pairs need an even n and one element");
 };
 
 // ---------------------------------------------------------------------------
@@ -576,17 +589,20 @@ struct VolLds {
 // shock capturing also the element's indicator value.
 // ---------------------------------------------------------------------------
 template <int N, typename real, bool SHOCK>
-__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const View<real> *views, const int *blk_start,
-                                                                         int nreq, View<real> single) {
+__global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, real, SHOCK>::minw))
+    k_volume(const View<real> *views, const int *blk_start, int nreq, View<real> single) {
   using S = Sz<N>;
   using L = VolLds<N, real, SHOCK>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
+  constexpr int npt = L::npt, tpe = L::tpe, kstep = n / npt;
   int lblk;
   const View<real> v = select_view(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
   __shared__ real sA[epb][L::rows];
   load_basis<N, real>(sb, v.basis);
-  const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
+  // thread a of an element holds its nodes a + m tpe, m < npt: the same i and
+  // j, and k = k0 + m kstep
+  const int le = threadIdx.x / tpe, a = threadIdx.x - le * tpe;
   const int64_t e = (int64_t)lblk * epb + le;
   const bool active = le < epb && e < v.E;
   real *const sm = sA[le < epb ? le : 0];
@@ -597,32 +613,37 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
   const bool visc = v.viscous != 0;  // the same for the whole grid
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
-  const int i = a % n, j = (a / n) % n, k = a / n2;
-  // when a wave is one k-plane of one element (n^2 = 64), the k row of D-hat
+  const int i = a % n, j = (a / n) % n, k0 = a / n2;
+  // when a wave is one k-plane of one element (n^2 = 64), the k rows of D-hat
   // and the face of a face node are the same on every lane: scalar loads
   // instead of LDS reads
-  constexpr bool plane_waves = n2 == 64 && epb == 1;
-  real dk[n];
+  constexpr bool plane_waves = L::plane_waves;
+  real dk[npt][n];
   if constexpr (plane_waves) {
-    const int ku = __builtin_amdgcn_readfirstlane(k);
+    const int ku = __builtin_amdgcn_readfirstlane(k0);
     const BasisOffsets o(n);
 #pragma unroll
-    for (int al = 0; al < n; ++al) dk[al] = v.basis[o.Dhat + ku * n + al];
+    for (int m = 0; m < npt; ++m)
+#pragma unroll
+      for (int al = 0; al < n; ++al) dk[m][al] = v.basis[o.Dhat + (ku + m * kstep) * n + al];
   }
-  real U[5];
+  real U[npt][5];
   real pf[L::upt][L::fpu][3];  // own face velocity at this thread's face nodes
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) U[c] = (real)(v.U + c * Ev)[vi];
+    for (int m = 0; m < npt; ++m)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) U[m][c] = (real)(v.U + c * Ev)[vi + m * tpe];
   }
   if constexpr (SHOCK) {
+    static_assert(npt == 1, "the indicator takes one node per thread");
     // a-priori indicator of this element (Sec. 2.3) on epsilon = rho p, in the
     // metric rows before they are filled; its neighbour propagation follows in
     // the surface sweep
     real eps = real(0);
     if (active) {
       real P[6];
-      cons2prim(U, gam, rR, P);
+      cons2prim(U[0], gam, rR, P);
       eps = P[0] * P[4];
     }
     const BasisOffsets o(n);
@@ -634,20 +655,24 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   }
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + a] = (v.Ja + c * Ev)[vi];
-    real P[6];
-    cons2prim(U, gam, rR, P);
-    sm[L::V + 0 * n3 + a] = P[1];
-    sm[L::V + 1 * n3 + a] = P[2];
-    sm[L::V + 2 * n3 + a] = P[3];
-    sm[L::V + 3 * n3 + a] = P[5];
+    for (int m = 0; m < npt; ++m) {
+      const int am = a + m * tpe;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + am] = (v.Ja + c * Ev)[vi + m * tpe];
+      real P[6];
+      cons2prim(U[m], gam, rR, P);
+      sm[L::V + 0 * n3 + am] = P[1];
+      sm[L::V + 1 * n3 + am] = P[2];
+      sm[L::V + 2 * n3 + am] = P[3];
+      sm[L::V + 3 * n3 + am] = P[5];
+    }
   }
   if (active && visc) {
     // Lift_FillFlux: the BR1 average of both sides' traces, and this side's
     // outward n shat and face velocity for its viscous flux later on
 #pragma unroll
     for (int r = 0; r < L::upt; ++r) {
-      const int t = a + r * n3;
+      const int t = a + r * tpe;
       if (t < L::units) {
         int d, s0, pq;
         face_unit<n, L::fpu, plane_waves>(t, d, s0, pq);
@@ -680,92 +705,146 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
     }
   }
   __syncthreads();
-  real Fc[15];  // contravariant fluxes Ja^i . (F_adv - F_v), i = 0..2
-  real g[12];
+  real Fc[npt][15];  // contravariant fluxes Ja^i . (F_adv - F_v), i = 0..2
+  real g[npt][12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) g[c] = real(0);
+  for (int m = 0; m < npt; ++m)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) g[m][c] = real(0);
   if (active && visc) {
-    // Lift_VolInt along the three computational directions
-    real JG[12];
+    // Lift_VolInt along the three computational directions.  Along xi and eta
+    // a thread's nodes share the D-hat row; along zeta they share the line.
+    real JG[npt][12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) JG[c] = real(0);
+    for (int m = 0; m < npt; ++m)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) JG[m][c] = real(0);
 #pragma unroll
     for (int ci = 0; ci < 3; ++ci) {
-      const int idx = ci == 0 ? i : (ci == 1 ? j : k);
       const real *Jr = sm + L::J + 3 * ci * n3;
 #pragma unroll
       for (int al = 0; al < n; ++al) {
-        const int src = ci == 0 ? vnode(n, al, j, k) : (ci == 1 ? vnode(n, i, al, k) : vnode(n, i, j, al));
-        const real dh = (plane_waves && ci == 2) ? dk[al] : sb.Dh[idx * (n + 1) + al];
-        // D-hat times the metric first: 3 products and 12 multiply-adds per source node
-        const real dj[3] = {dh * Jr[src], dh * Jr[n3 + src], dh * Jr[2 * n3 + src]};
-        const real vv[4] = {sm[L::V + src], sm[L::V + n3 + src], sm[L::V + 2 * n3 + src], sm[L::V + 3 * n3 + src]};
+        if (ci < 2) {
+          const real dh = sb.Dh[(ci == 0 ? i : j) * (n + 1) + al];
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+          for (int m = 0; m < npt; ++m) {
+            const int km = k0 + m * kstep;
+            const int src = ci == 0 ? vnode(n, al, j, km) : vnode(n, i, al, km);
+            // D-hat times the metric first: 3 products and 12 multiply-adds per source node
+            const real dj[3] = {dh * Jr[src], dh * Jr[n3 + src], dh * Jr[2 * n3 + src]};
+            const real vv[4] = {sm[L::V + src], sm[L::V + n3 + src], sm[L::V + 2 * n3 + src],
+                                sm[L::V + 3 * n3 + src]};
 #pragma unroll
-          for (int s = 0; s < 4; ++s) JG[d * 4 + s] += dj[d] * vv[s];
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+              for (int s = 0; s < 4; ++s) JG[m][d * 4 + s] += dj[d] * vv[s];
+          }
+        } else {
+          const int src = vnode(n, i, j, al);
+          const real jr[3] = {Jr[src], Jr[n3 + src], Jr[2 * n3 + src]};
+          const real vv[4] = {sm[L::V + src], sm[L::V + n3 + src], sm[L::V + 2 * n3 + src], sm[L::V + 3 * n3 + src]};
+#pragma unroll
+          for (int m = 0; m < npt; ++m) {
+            const real dh = plane_waves ? dk[m][al] : sb.Dh[(k0 + m * kstep) * (n + 1) + al];
+            const real dj[3] = {dh * jr[0], dh * jr[1], dh * jr[2]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+              for (int s = 0; s < 4; ++s) JG[m][d * 4 + s] += dj[d] * vv[s];
+          }
+        }
       }
     }
     // Lift_SurfInt: the face average times n shat, through l-hat
-    const int pqf[3] = {j + n * k, i + n * k, i + n * j};
-    const int lf[3] = {i, j, k};
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1;
-      const real lh = (f & 1) ? sb.lhp[lf[d]] : sb.lhm[lf[d]];
-      const int fn = f * n2 + pqf[d];
-      const real av[4] = {sm[L::Avg + fn], sm[L::Avg + nf + fn], sm[L::Avg + 2 * nf + fn], sm[L::Avg + 3 * nf + fn]};
+      if (d < 2) {
+        const real lh = (f & 1) ? sb.lhp[d == 0 ? i : j] : sb.lhm[d == 0 ? i : j];
 #pragma unroll
-      for (int dd = 0; dd < 3; ++dd) {
-        const real nl = sm[L::Ns + dd * nf + fn] * lh;
+        for (int m = 0; m < npt; ++m) {
+          const int km = k0 + m * kstep;
+          const int fn = f * n2 + (d == 0 ? j : i) + n * km;
+          const real av[4] = {sm[L::Avg + fn], sm[L::Avg + nf + fn], sm[L::Avg + 2 * nf + fn],
+                              sm[L::Avg + 3 * nf + fn]};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) JG[dd * 4 + s] += av[s] * nl;
+          for (int dd = 0; dd < 3; ++dd) {
+            const real nl = sm[L::Ns + dd * nf + fn] * lh;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) JG[m][dd * 4 + s] += av[s] * nl;
+          }
+        }
+      } else {
+        const int fn = f * n2 + i + n * j;
+        const real av[4] = {sm[L::Avg + fn], sm[L::Avg + nf + fn], sm[L::Avg + 2 * nf + fn], sm[L::Avg + 3 * nf + fn]};
+        const real ns[3] = {sm[L::Ns + fn], sm[L::Ns + nf + fn], sm[L::Ns + 2 * nf + fn]};
+#pragma unroll
+        for (int m = 0; m < npt; ++m) {
+          const int km = k0 + m * kstep;
+          const real lh = (f & 1) ? sb.lhp[km] : sb.lhm[km];
+#pragma unroll
+          for (int dd = 0; dd < 3; ++dd) {
+            const real nl = ns[dd] * lh;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) JG[m][dd * 4 + s] += av[s] * nl;
+          }
+        }
       }
     }
-    const real iJ = v.invJ[vi];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) g[c] = JG[c] * iJ;
+    for (int m = 0; m < npt; ++m) {
+      const real iJ = v.invJ[vi + m * tpe];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) g[m][c] = JG[m][c] * iJ;
+    }
   }
   if (active) {
-    // volume fluxes at this node, projected on the three contravariant directions
-    real P[6];
-    cons2prim(U, gam, rR, P);
-    real Fx[5], Fy[5], Fz[5];
-    flux_adv<0>(U, P, Fx);
-    flux_adv<1>(U, P, Fy);
-    flux_adv<2>(U, P, Fz);
-    if (visc) {
-      real Vx[5], Vy[5], Vz[5];
-      flux_visc<0>(P, g, mu, lam, Vx);
-      flux_visc<1>(P, g, mu, lam, Vy);
-      flux_visc<2>(P, g, mu, lam, Vz);
+    // volume fluxes at each node, projected on the three contravariant directions
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        Fx[c] -= Vx[c];
-        Fy[c] -= Vy[c];
-        Fz[c] -= Vz[c];
+    for (int m = 0; m < npt; ++m) {
+      const int am = a + m * tpe;
+      real P[6];
+      cons2prim(U[m], gam, rR, P);
+      real Fx[5], Fy[5], Fz[5];
+      flux_adv<0>(U[m], P, Fx);
+      flux_adv<1>(U[m], P, Fy);
+      flux_adv<2>(U[m], P, Fz);
+      if (visc) {
+        real Vx[5], Vy[5], Vz[5];
+        flux_visc<0>(P, g[m], mu, lam, Vx);
+        flux_visc<1>(P, g[m], mu, lam, Vy);
+        flux_visc<2>(P, g[m], mu, lam, Vz);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          Fx[c] -= Vx[c];
+          Fy[c] -= Vy[c];
+          Fz[c] -= Vz[c];
+        }
       }
-    }
 #pragma unroll
-    for (int ci = 0; ci < 3; ++ci) {
-      const real j0 = sm[L::J + (3 * ci) * n3 + a], j1 = sm[L::J + (3 * ci + 1) * n3 + a],
-                 j2 = sm[L::J + (3 * ci + 2) * n3 + a];
+      for (int ci = 0; ci < 3; ++ci) {
+        const real j0 = sm[L::J + (3 * ci) * n3 + am], j1 = sm[L::J + (3 * ci + 1) * n3 + am],
+                   j2 = sm[L::J + (3 * ci + 2) * n3 + am];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) Fc[5 * ci + c] = j0 * Fx[c] + j1 * Fy[c] + j2 * Fz[c];
+        for (int c = 0; c < 5; ++c) Fc[m][5 * ci + c] = j0 * Fx[c] + j1 * Fy[c] + j2 * Fz[c];
+      }
     }
   }
   __syncthreads();  // the rows read above are covered by g below
   if (active && visc) {
-    const int pa = Pad<n>::at(i, j, k);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) sm[L::G + c * L::gsz + pa] = g[c];
+    for (int m = 0; m < npt; ++m) {
+      const int pa = Pad<n>::at(i, j, k0 + m * kstep);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sm[L::G + c * L::gsz + pa] = g[m][c];
+    }
   }
   __syncthreads();
   if (active && visc) {
     // Lift_ProlongToFace of g, then this side's viscous normal flux
 #pragma unroll
     for (int r = 0; r < L::upt; ++r) {
-      const int t = a + r * n3;
+      const int t = a + r * tpe;
       if (t < L::units) {
         int d, s0, pq;
         face_unit<n, L::fpu, plane_waves>(t, d, s0, pq);
@@ -831,24 +910,48 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_volume(const Vi
   // VolInt: the fluxes of all three directions at once
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 15; ++c) sm[L::F + c * n3 + a] = Fc[c];
+    for (int m = 0; m < npt; ++m)
+#pragma unroll
+      for (int c = 0; c < 15; ++c) sm[L::F + c * n3 + a + m * tpe] = Fc[m][c];
   }
   __syncthreads();
   if (active) {
-    real Vi[5] = {0, 0, 0, 0, 0};
+    real Vi[npt][5];
+#pragma unroll
+    for (int m = 0; m < npt; ++m)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Vi[m][c] = real(0);
 #pragma unroll
     for (int ci = 0; ci < 3; ++ci) {
-      const int idx = ci == 0 ? i : (ci == 1 ? j : k);
 #pragma unroll
       for (int alp = 0; alp < n; ++alp) {
-        const int src = ci == 0 ? vnode(n, alp, j, k) : (ci == 1 ? vnode(n, i, alp, k) : vnode(n, i, j, alp));
-        const real dh = (plane_waves && ci == 2) ? dk[alp] : sb.Dh[idx * (n + 1) + alp];
+        if (ci < 2) {
+          const real dh = sb.Dh[(ci == 0 ? i : j) * (n + 1) + alp];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) Vi[c] += dh * sm[L::F + (5 * ci + c) * n3 + src];
+          for (int m = 0; m < npt; ++m) {
+            const int km = k0 + m * kstep;
+            const int src = ci == 0 ? vnode(n, alp, j, km) : vnode(n, i, alp, km);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Vi[m][c] += dh * sm[L::F + (5 * ci + c) * n3 + src];
+          }
+        } else {
+          const int src = vnode(n, i, j, alp);
+          real fz[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) fz[c] = sm[L::F + (10 + c) * n3 + src];
+#pragma unroll
+          for (int m = 0; m < npt; ++m) {
+            const real dh = plane_waves ? dk[m][alp] : sb.Dh[(k0 + m * kstep) * (n + 1) + alp];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Vi[m][c] += dh * fz[c];
+          }
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < 5; ++c) (v.Vol + c * Ev)[vi] = Vi[c];
+    for (int m = 0; m < npt; ++m)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) (v.Vol + c * Ev)[vi + m * tpe] = Vi[m][c];
   }
 }
 
@@ -1253,12 +1356,12 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
       // volume sweep: indicator (shock capturing), lifting (viscous), VolInt
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          k_volume<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+          k_volume<N, real, true><<<grid, (VolLds<N, real, true>::threads), 0, st>>>(views, blk_start, nreq, v0);
         } else {
           return hipErrorInvalidValue;
         }
       } else {
-        k_volume<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+        k_volume<N, real, false><<<grid, (VolLds<N, real, false>::threads), 0, st>>>(views, blk_start, nreq, v0);
       }
       break;
     case K_RHS:
