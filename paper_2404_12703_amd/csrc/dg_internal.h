@@ -40,12 +40,15 @@ struct View {
   real *alpha;      // [E] blending factors
   real *alpha_raw;  // [E] indicator values before neighbour propagation
   const real *alpha_in; // [E] frozen blending factors or null
+  int *bcnt;        // shock capturing: [2] entries of blist, used by alternate surface sweeps
+  int *blist;       // shock capturing: [E] workgroups with a blended element, this sweep
   char *base;       // batched launches, in the argument view: the arena that the
                     // descriptors' pointer fields are byte offsets into
   real gamma, Rgas, rRgas, mu, lambda; // perfect gas (rRgas = 1/R), constant viscosity and conductivity
   double Pr;        // Prandtl number (time-step estimate only)
   double t, dt, rkA, rkB;       // stage time, step, LSERK coefficients
   int cur;          // trace buffer read this stage (0: Utr0, 1: Utr1)
+  int bpar;         // entry of bcnt this surface sweep counts in; it clears the other
   int viscous, riemann, source, shock;
   int remap;        // XCD-contiguous block order (single solve)
   real ind_a, ind_c, ind_s, alpha_min, alpha_max, ind_T; // indicator (ind_T precomputed threshold)

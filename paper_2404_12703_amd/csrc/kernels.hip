@@ -98,22 +98,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return start + idx;
 }
 
+// the descriptors of a batch hold byte offsets into the arena; rebuilding the
+// pointers from the argument's arena pointer keeps every access a global-memory
+// one (pointers read from memory would be addressed as generic pointers)
 template <typename real>
-__device__ __forceinline__ View<real> select_view(const View<real> *views, const int *blk_start, int nreq,
-                                                  const View<real> &single, int &lblk) {
-  if (nreq == 0) {
-    lblk = single.remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    return single;
-  }
-  const int b = blockIdx.x;
-  int r = 0;
-  while (r + 1 < nreq && b >= blk_start[r + 1]) ++r;
-  lblk = b - blk_start[r];
-  // the descriptors hold byte offsets into the arena; rebuilding the pointers
-  // from the argument's arena pointer keeps every access a global-memory one
-  // (pointers read from memory would be addressed as generic pointers)
-  View<real> v = views[r];
-  char *const base = single.base;
+__device__ __forceinline__ View<real> rebase(View<real> v, char *const base) {
   auto at = [base](auto p) { return (decltype(p))(base + (intptr_t)p); };
   auto at_or_null = [base](auto p) { return p ? (decltype(p))(base + (intptr_t)p) : p; };
   v.U = at(v.U);
@@ -132,7 +121,23 @@ __device__ __forceinline__ View<real> select_view(const View<real> *views, const
   v.alpha = at(v.alpha);
   v.alpha_raw = at(v.alpha_raw);
   v.alpha_in = at_or_null(v.alpha_in);
+  v.bcnt = at_or_null(v.bcnt);
+  v.blist = at_or_null(v.blist);
   return v;
+}
+
+template <typename real>
+__device__ __forceinline__ View<real> select_view(const View<real> *views, const int *blk_start, int nreq,
+                                                  const View<real> &single, int &lblk) {
+  if (nreq == 0) {
+    lblk = single.remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    return single;
+  }
+  const int b = blockIdx.x;
+  int r = 0;
+  while (r + 1 < nreq && b >= blk_start[r + 1]) ++r;
+  lblk = b - blk_start[r];
+  return rebase(views[r], single.base);
 }
 
 template <int N, typename real>
@@ -197,55 +202,98 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *view
 
 // ---------------------------------------------------------------------------
 // a-priori indicator (Sec. 2.3): modal energy of eps = rho p.  m = (V^-1 (x)
-// V^-1 (x) V^-1) eps by three line transforms through LDS rows r0..r2, then a
-// fixed-order tree reduction of the energies in rows r3..r5 (no atomics, so
-// the value is reproducible).  Every thread of the block must call it.
+// V^-1 (x) V^-1) eps by three line transforms through LDS rows r0..r2 (V^-1
+// staged in vs), then fixed-order sums of the energies (no atomics, so the
+// value is reproducible): within each wave by lane exchanges and over the
+// waves of the element through r3..r5 where elements and waves align, else a
+// tree through r3..r5.  Every thread of the block must call it.
 // Returns the clipped logistic value on thread a == 0 of each element.
 // ---------------------------------------------------------------------------
 template <int N, typename real>
 __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *Vinv, real *r0, real *r1, real *r2,
-                                              real *r3, real *r4, real *r5, bool active, int a, real eps) {
+                                              real *r3, real *r4, real *r5, real *vs, bool active, int a, real eps) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
   const int i = a % n, j = (a / n) % n, k = a / n2;
-  if (active) r0[a] = eps;
+  if (active) {
+    for (int t = a; t < n2; t += n3) vs[t] = Vinv[t];
+    r0[a] = eps;
+  }
   __syncthreads();
   if (active) {
     real t = real(0);
 #pragma unroll
-    for (int r = 0; r < n; ++r) t += Vinv[i * n + r] * r0[vnode(n, r, j, k)];
+    for (int r = 0; r < n; ++r) t += vs[i * n + r] * r0[vnode(n, r, j, k)];
     r1[a] = t;
   }
   __syncthreads();
   if (active) {
     real t = real(0);
 #pragma unroll
-    for (int r = 0; r < n; ++r) t += Vinv[j * n + r] * r1[vnode(n, i, r, k)];
+    for (int r = 0; r < n; ++r) t += vs[j * n + r] * r1[vnode(n, i, r, k)];
     r2[a] = t;
   }
   __syncthreads();
+  real e0 = real(0), e1 = real(0), e2 = real(0);  // energies: all modes, degrees <= N-1, <= N-2
   if (active) {
     real m = real(0);
 #pragma unroll
-    for (int r = 0; r < n; ++r) m += Vinv[k * n + r] * r2[vnode(n, i, j, r)];
-    const real m2 = m * m;
-    r3[a] = m2;
-    r4[a] = (i < N && j < N && k < N) ? m2 : real(0);
-    r5[a] = (i < N - 1 && j < N - 1 && k < N - 1) ? m2 : real(0);
+    for (int r = 0; r < n; ++r) m += vs[k * n + r] * r2[vnode(n, i, j, r)];
+    e0 = m * m;
+    e1 = (i < N && j < N && k < N) ? e0 : real(0);
+    e2 = (i < N - 1 && j < N - 1 && k < N - 1) ? e0 : real(0);
   }
-  __syncthreads();
-  constexpr int P2 = n3 <= 8 ? 8 : (n3 <= 16 ? 16 : (n3 <= 32 ? 32 : (n3 <= 64 ? 64 : (n3 <= 128 ? 128 : (n3 <= 256 ? 256 : (n3 <= 512 ? 512 : 1024))))));
+  // each element's nodes fill whole waves (or the element is alone in the
+  // workgroup): reduce within waves, then over the element's waves
+  constexpr bool wave_sums = (n3 % 64 == 0) || Sz<N>::epb == 1;
+  real tot = real(0), c1 = real(0), c2 = real(0);
+  if constexpr (wave_sums) {
+    // every lane takes part; lanes without a node add zeros
 #pragma unroll
-  for (int st = P2 / 2; st > 0; st >>= 1) {
-    if (active && a < st && a + st < n3) {
-      r3[a] += r3[a + st];
-      r4[a] += r4[a + st];
-      r5[a] += r5[a + st];
+    for (int off = 32; off > 0; off >>= 1) {
+      e0 += __shfl_xor(e0, off, 64);
+      e1 += __shfl_xor(e1, off, 64);
+      e2 += __shfl_xor(e2, off, 64);
+    }
+    constexpr int W = (n3 + 63) / 64;
+    if (active && (a & 63) == 0) {
+      r3[a >> 6] = e0;
+      r4[a >> 6] = e1;
+      r5[a >> 6] = e2;
     }
     __syncthreads();
+    if (active && a == 0) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        tot += r3[w];
+        c1 += r4[w];
+        c2 += r5[w];
+      }
+    }
+  } else {
+    if (active) {
+      r3[a] = e0;
+      r4[a] = e1;
+      r5[a] = e2;
+    }
+    __syncthreads();
+    constexpr int P2 = n3 <= 8 ? 8 : (n3 <= 16 ? 16 : (n3 <= 32 ? 32 : (n3 <= 64 ? 64 : (n3 <= 128 ? 128 : (n3 <= 256 ? 256 : (n3 <= 512 ? 512 : 1024))))));
+#pragma unroll
+    for (int st = P2 / 2; st > 0; st >>= 1) {
+      if (active && a < st && a + st < n3) {
+        r3[a] += r3[a + st];
+        r4[a] += r4[a + st];
+        r5[a] += r5[a + st];
+      }
+      __syncthreads();
+    }
+    if (active && a == 0) {
+      tot = r3[0];
+      c1 = r4[0];
+      c2 = r5[0];
+    }
   }
   real alpha = real(0);
   if (active && a == 0) {
-    const real tot = r3[0], c1 = r4[0], c2 = r5[0];
     const real E1 = tot > real(0) ? (tot - c1) / tot : real(0);
     const real E2 = c1 > real(0) ? (c1 - c2) / c1 : real(0);
     const real Ev = fmax(E1, E2);
@@ -649,7 +697,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
     const BasisOffsets o(n);
     real *r = sm + L::J;
     const real al = indicator_raw<N, real>(v, v.basis + o.Vinv, r, r + n3, r + 2 * n3, r + 3 * n3, r + 4 * n3,
-                                           r + 5 * n3, active, a, eps);
+                                           r + 5 * n3, r + 6 * n3, active, a, eps);
     if (active && a == 0) v.alpha_raw[e] = al;
     __syncthreads();
   }
@@ -956,29 +1004,31 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
 }
 
 // ---------------------------------------------------------------------------
-// Surface sweep: FillFlux from this side's recomputed U trace, the
-// neighbour's stored one and the mean of both sides' H; with shock capturing
-// the blend of the FV subcell operator; SurfInt gather, ApplyJac, the stage
-// update (mode 0) or R (mode 1), and the next U traces.
+// Surface sweep of one workgroup of elements: FillFlux from this side's
+// recomputed U trace, the neighbour's stored one and the mean of both sides'
+// H; SurfInt gather, ApplyJac, the stage update (mode 0) or R (mode 1), and
+// the next U traces.  SH = 1 (shock capturing, first pass) also forms the
+// blending factors and hands a workgroup with a blended element to the blend
+// pass; SH = 2 (the blend pass) adds the FV subcell operator.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool SHOCK>
-__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
-                                                                          int nreq, View<real> single, int mode) {
+template <int N, typename real, int SH>
+__device__ __forceinline__ void surface_body(const View<real> &v, const int lblk, const int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
-  int lblk;
-  const View<real> v = select_view(views, blk_start, nreq, single, lblk);
+  constexpr bool SHOCK = SH != 0, FV = SH == 2;
   __shared__ Smem<N, real> sb;
   __shared__ real sB[epb][5][Pad<n>::size];
   __shared__ real sS[epb][5][nf];
-  // shock capturing: 16 rows per element for the subcell operator and the
-  // advective volume integral, the 1-D operators of the subcells, alpha
-  __shared__ real sX[SHOCK ? epb * 16 * n3 : 1];
-  __shared__ real sFV[SHOCK ? (n * n + 3 * n + 1) : 1];  // D, w, x, xhalf
+  // the blend pass: 16 rows per element for the subcell operator and the
+  // advective volume integral, the 1-D operators of the subcells
+  __shared__ real sX[FV ? epb * 16 * n3 : 1];
+  __shared__ real sFV[FV ? (n * n + 3 * n + 1) : 1];  // D, w, x, xhalf
   __shared__ real sAl[epb];
-  __shared__ int sAny;
   load_basis<N, real>(sb, v.basis);
-  if constexpr (SHOCK) {
+  // the first pass clears the count of the next sweep (which alternates
+  // entries, so no pass reads a count that another pass clears)
+  if (SH == 1 && lblk == 0 && threadIdx.x == 0) v.bcnt[1 - v.bpar] = 0;
+  if constexpr (FV) {
     const BasisOffsets o(n);
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) sFV[t] = v.basis[o.D + t];
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
@@ -986,7 +1036,6 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
       sFV[n * n + n + t] = v.basis[o.x + t];
     }
     for (int t = threadIdx.x; t < n + 1; t += blockDim.x) sFV[n * n + 2 * n + t] = v.basis[o.xhalf + t];
-    if (threadIdx.x == 0) sAny = 0;
   }
   const int le = threadIdx.x / n3, a = threadIdx.x - le * n3;
   const int64_t e = (int64_t)lblk * epb + le;
@@ -1003,9 +1052,9 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
   // the state, in LDS for this element's own traces and for the update.  The
   // FP64 copy is exact, so it is read back after the face phase instead of
   // being held in registers through it (they would spill); the mixed form
-  // keeps the FP64 values, and so does the shock-capturing sweep, whose
-  // occupancy its LDS sets.
-  constexpr bool exact_lds = sizeof(real) == sizeof(double) && !SHOCK;
+  // keeps the FP64 values, and so does the blend pass, whose occupancy its
+  // LDS sets.
+  constexpr bool exact_lds = sizeof(real) == sizeof(double) && !FV;
   double Uold[5] = {0, 0, 0, 0, 0};
   if (active) {
 #pragma unroll
@@ -1013,10 +1062,12 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
       Uold[c] = (v.U + c * Ev)[vi];
       su[c * Pad<n>::size + pa] = (real)Uold[c];
     }
-    if (SHOCK && a == 0) {
-      // blending factor: frozen, or the element's indicator value raised to
-      // half of its face neighbours' (Sec. 2.3)
-      real a0;
+  }
+  if (SHOCK && le < epb && a == 0) {
+    // blending factor: frozen, or the element's indicator value raised to
+    // half of its face neighbours' (Sec. 2.3); zero past the last element
+    real a0 = real(0);
+    if (active) {
       if (v.alpha_in) {
         a0 = v.alpha_in[e];
       } else {
@@ -1025,16 +1076,25 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
         for (int f = 0; f < 6; ++f) a0 = fmax(a0, real(0.5) * v.alpha_raw[v.conn[e * 6 + f].x / 6]);
         a0 = fmin(a0, v.alpha_max);
       }
-      sAl[le] = a0;
     }
+    sAl[le] = a0;
   }
   __syncthreads();
   real al = real(0);
+  bool any = false;  // some element of the workgroup is blended
   if constexpr (SHOCK) {
+#pragma unroll
+    for (int q = 0; q < epb; ++q) any = any || sAl[q] > real(0);
     if (active) {
       al = sAl[le];
       if (a == 0) v.alpha[e] = al;
-      if (al > real(0)) sAny = 1;  // every writer stores 1; read after the next barrier
+    }
+    if constexpr (SH == 1) {
+      // a workgroup with a blended element is left to the blend pass
+      if (any) {
+        if (threadIdx.x == 0) v.blist[atomicAdd(v.bcnt + v.bpar, 1)] = lblk;
+        return;
+      }
     }
   }
   if (active) {
@@ -1096,8 +1156,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
   // blended elements: alpha (V_FV - V_adv) joins the stored volume integral,
   // i.e. (1 - alpha) V_adv + alpha V_FV + V_visc
   real Vb[5] = {0, 0, 0, 0, 0};
-  if constexpr (SHOCK) {
-    if (sAny) {  // the same on every thread of the workgroup
+  if constexpr (FV) {
+    if (any) {  // the same on every thread of the workgroup
       real *rows = sX + (le < epb ? le : 0) * 16 * n3;
       real U[5], P[6], Ja[9];
       if (active) {
@@ -1204,6 +1264,34 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const V
 #pragma unroll
         for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
       }
+    }
+  }
+}
+
+
+// Surface sweep: SH = 0 without shock capturing; SH = 1 with it, for the
+// workgroups without a blended element (the others are listed for k_blend).
+template <int N, typename real, int SH>
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
+                                                                          int nreq, View<real> single, int mode) {
+  int lblk;
+  const View<real> v = select_view(views, blk_start, nreq, single, lblk);
+  surface_body<N, real, SH>(v, lblk, mode);
+}
+
+// Blend pass: the surface sweep with the FV subcell blend, for the workgroups
+// that k_surface<SH = 1> listed, request by request; a fixed grid strides over
+// each list.
+template <int N, typename real>
+__global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_blend(const View<real> *views, int nreq,
+                                                                        View<real> single, int mode) {
+  const int nr = nreq == 0 ? 1 : nreq;
+  for (int r = 0; r < nr; ++r) {
+    const View<real> v = nreq == 0 ? single : rebase(views[r], single.base);
+    const int cnt = v.bcnt[v.bpar];
+    for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
+      surface_body<N, real, 2>(v, v.blist[idx], mode);
+      __syncthreads();  // LDS is reused by the next listed workgroup
     }
   }
 }
@@ -1344,6 +1432,9 @@ int block_threads(int N) {
   return 0;
 }
 
+// workgroups of the blend pass: one per CU
+constexpr int kBlendBlocks = 256;
+
 template <int N, typename real>
 static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const int *blk_start, int nreq, int blocks,
                            const View<real> &v0, hipStream_t st) {
@@ -1368,12 +1459,13 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
       // surface sweep (after a volume sweep), or the one-sweep Euler operator
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          k_surface<N, real, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          k_surface<N, real, 1><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          k_blend<N, real><<<std::min(blocks, kBlendBlocks), block, 0, st>>>(views, nreq, v0, mode);
         } else {
           return hipErrorInvalidValue;
         }
       } else if (v0.viscous) {
-        k_surface<N, real, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        k_surface<N, real, 0><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       } else {
         k_rhs<N, real><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       }

@@ -61,7 +61,7 @@ struct Request {
   Layout L{};
   View<double> vd{};
   View<float> vf{};
-  int step = 0, stage = 0, cur = 0;
+  int step = 0, stage = 0, cur = 0, bpar = 0;  // bpar: alternates over surface sweeps
   double t = 0.0;
   bool traces_valid = false;
   // host set-up, made by the preparation thread once the request has arrived;
@@ -338,7 +338,7 @@ dg_status admit(dg_server *sv) {
     r.state = DG_REQ_RUNNING;
     r.t_admit = sv->now();
     r.t = 0.0;
-    r.step = r.stage = r.cur = 0;
+    r.step = r.stage = r.cur = r.bpar = 0;
     r.traces_valid = false;
     sv->active.push_back(r.id);
     if (r.n_steps == 0) r.step = r.n_steps;
@@ -378,6 +378,8 @@ View<real> as_offsets(View<real> v, const char *arena) {
   v.alpha = off(v.alpha);
   v.alpha_raw = off(v.alpha_raw);
   v.alpha_in = off(v.alpha_in);
+  v.bcnt = off(v.bcnt);
+  v.blist = off(v.blist);
   return v;
 }
 
@@ -401,6 +403,7 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
     v.rkA = RK_A[q.stage];
     v.rkB = RK_B[q.stage];
     v.cur = q.cur;
+    v.bpar = q.bpar;
     v.R = nullptr;
     views[r] = as_offsets(v, sv->arena);
     blk[r] = total;
@@ -447,6 +450,7 @@ dg_status tick(dg_server *sv) {
     for (Request *r : kv.second) {
       r->traces_valid = true;
       r->cur ^= 1;
+      r->bpar ^= 1;
       if (++r->stage == 5) {
         r->stage = 0;
         ++r->step;

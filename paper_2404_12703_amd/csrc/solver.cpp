@@ -87,6 +87,9 @@ Layout make_layout(const dg_params &p, int64_t E) {
   L.alpha = take(E * rs);
   L.alpha_raw = take(E * rs);
   L.alpha_in = take(E * rs);
+  // shock capturing: the workgroups left to the blend pass (two counts,
+  // used by alternate surface sweeps, and at most one entry per element)
+  L.blend = p.shock_capturing ? take((2 + E) * sizeof(int)) : SIZE_MAX;
   L.scratch = take(kRedBlocks * 8 * sizeof(double));
   L.total = o;
   return L;
@@ -113,6 +116,8 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.alpha = (real *)at(L.alpha);
   v.alpha_raw = (real *)at(L.alpha_raw);
   v.alpha_in = nullptr;
+  v.bcnt = (int *)at(L.blend);
+  v.blist = v.bcnt ? v.bcnt + 2 : nullptr;
   v.base = nullptr;
   v.gamma = (real)p.gamma;
   v.Rgas = (real)p.R;
@@ -277,6 +282,7 @@ static hipError_t stage(dg_solver *s, int mode, double t, double dt, double A, d
   v.rkA = A;
   v.rkB = B;
   v.cur = s->cur;
+  v.bpar = s->bpar;
   v.R = Rout;
   hipError_t e = hipSuccess;
   if (!s->traces_valid) {
@@ -290,6 +296,7 @@ static hipError_t stage(dg_solver *s, int mode, double t, double dt, double A, d
   }
   e = run_kernel<real>(s, K_RHS, mode, v);
   if (e != hipSuccess) return e;
+  s->bpar ^= 1;
   if (mode == 0) s->cur ^= 1;
   return hipSuccess;
 }

@@ -14,7 +14,7 @@ constexpr int kRedBlocks = 1024;  // blocks of the reduction kernels
 
 // byte offsets of every array inside the caller's workspace (SIZE_MAX: absent)
 struct Layout {
-  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Hv, Vol, conn, Xs, basis, alpha, alpha_raw, alpha_in, scratch, total;
+  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Hv, Vol, conn, Xs, basis, alpha, alpha_raw, alpha_in, blend, scratch, total;
 };
 
 Layout make_layout(const dg_params &p, int64_t E);
@@ -74,6 +74,7 @@ struct dg_solver {
   dg::View<float> vf{};
   double t = 0.0;
   int cur = 0;
+  int bpar = 0;  // alternates over surface sweeps (blend-pass list counts)
   bool traces_valid = false;
   bool prof_on = false;
   std::vector<dg::ProfEvent> prof_events;

@@ -63,6 +63,36 @@ def test_batched_equals_alone_bitwise():
         assert np.array_equal(U, _alone(wl, dt)), (req, wl.params["precision"])
 
 
+def test_batched_blast_equals_alone_bitwise():
+    """Shock-capturing requests: workgroups with a blended element go to the
+    blend pass, which walks every request's list in one launch."""
+    import paper_2404_12703_amd as P
+    _say("[server] blast requests, N = 5 and 3, FP64 and mixed")
+    wls = []
+    for K, N, seed, prec in ((4, 5, 1, 0), (5, 5, 2, 0), (4, 3, 3, 0), (6, 3, 4, 0), (4, 5, 5, 1)):
+        wl = W.blast_workload(K=K, N=N, steps=3, seed=seed)
+        wl.params = dict(wl.params, precision=prec)
+        wls.append(wl)
+    sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=8)
+    ids, dts, blended = [], [], []
+    for wl in wls:
+        s = P.Solver(wl.params, wl.mesh)
+        s.set_state(wl.U0)
+        dts.append(s.stable_dt(wl.cfl, wl.cfl))
+        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, wl.steps, dts[-1], 0.0))
+    sv.run(0)
+    for wl, rid, dt in zip(wls, ids, dts):
+        assert sv.poll(rid) == P.REQ_DONE
+        U, _ = sv.fetch(rid)
+        s = P.Solver(wl.params, wl.mesh)
+        s.set_state(wl.U0)
+        s.advance(wl.steps, dt)
+        assert np.array_equal(U, s.state()), (wl.mesh.n_elems, wl.params["N"], wl.params["precision"])
+        blended.append(int(np.sum(s.alpha() > 0)))
+    _say(f"[server] blended elements after 3 steps: {blended}")
+    assert max(blended) > 0
+
+
 def test_poisoned_request_fails_alone_and_budget_binds():
     import paper_2404_12703_amd as P
     reqs = _requests(6, 1, precision_mix=False)
