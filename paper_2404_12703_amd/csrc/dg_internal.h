@@ -50,6 +50,7 @@ struct View {
   int cur;          // trace buffer read this stage (0: Utr0, 1: Utr1)
   int bpar;         // entry of bcnt this surface sweep counts in; it clears the other
   int viscous, riemann, source, shock;
+  int lgl;          // Gauss-Lobatto nodes: l(-1), l(+1) are unit vectors, l-hat vanishes off the end nodes
   int remap;        // XCD-contiguous block order (single solve)
   real ind_a, ind_c, ind_s, alpha_min, alpha_max, ind_T; // indicator (ind_T precomputed threshold)
 };

@@ -12,13 +12,15 @@
 //              BR1 lifting with g kept on chip; each own face node's viscous
 //              normal flux; the whole volume integral.
 //   k_surface: (shock capturing) the blending factor from the neighbours'
-//              indicator values and, where it is positive, the FV subcell
-//              operator; the face fluxes (Riemann + BR1 viscous mean) of the
-//              six faces, computed by both neighbours from the same operands
-//              in the same order so both hold the same bits and nothing is
-//              stored; the per-DOF SurfInt gather (one writer per entry, as
-//              the paper's GPU SurfInt); ApplyJac; the LSERK stage update; and
-//              the next stage's U traces (ProlongToFace).
+//              indicator values; the face fluxes (Riemann + BR1 viscous
+//              mean) of the six faces, computed by both neighbours from the
+//              same operands in the same order so both hold the same bits
+//              and nothing is stored; the per-DOF SurfInt gather (one writer
+//              per entry, as the paper's GPU SurfInt); ApplyJac; the LSERK
+//              stage update; and the next stage's U traces (ProlongToFace).
+//   k_blend  : (shock capturing) the same for the workgroups holding an
+//              element with a positive blending factor, which k_surface lists
+//              and skips, plus the FV subcell operator.
 // Euler without shock capturing takes one sweep, k_rhs.
 // Traces are ping-ponged between stages because the last sweep reads the
 // neighbours' traces of the old state while writing those of the new one.
@@ -81,6 +83,20 @@ __device__ __forceinline__ void prolong_state(const real *rows, const real *lv, 
   }
 #pragma unroll
   for (int c = 0; c < 5; ++c) out[c] = s[c];
+}
+
+// The conservative state at one face node: with Gauss-Lobatto nodes the end
+// node of the line (l(-1), l(+1) are unit vectors), else ProlongToFace.
+template <int n, bool LGL, typename real>
+__device__ __forceinline__ void face_state(const real *rows, const real *lv, int base, int stride, bool plus,
+                                           real *out) {
+  if constexpr (LGL) {
+    const int at = base + (plus ? (n - 1) * stride : 0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = rows[c * Pad<n>::size + at];
+  } else {
+    prolong_state<n>(rows, lv, base, stride, out);
+  }
 }
 
 // which view and which element block this workgroup works on: a single
@@ -164,7 +180,7 @@ __device__ __forceinline__ void load_basis(Smem<N, real> &sb, const real *basis)
 // ---------------------------------------------------------------------------
 // ProlongToFace of the state into the current trace buffer
 // ---------------------------------------------------------------------------
-template <int N, typename real>
+template <int N, typename real, bool LGL>
 __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *views, const int *blk_start, int nreq,
                                                          View<real> single) {
   using S = Sz<N>;
@@ -193,7 +209,7 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *view
       int base, stride;
       Pad<n>::face_line(f, pq, base, stride);
       real t[5];
-      prolong_state<n>(su, (f & 1) ? sb.lp : sb.lm, base, stride, t);
+      face_state<n, LGL>(su, (f & 1) ? sb.lp : sb.lm, base, stride, f & 1, t);
 #pragma unroll
       for (int c = 0; c < 5; ++c) (tr + c * Ef)[fb + fn] = t[c];
     }
@@ -636,7 +652,7 @@ struct VolLds {
 // the mass component is zero) and the volume integral (5 per node); with
 // shock capturing also the element's indicator value.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool SHOCK>
+template <int N, typename real, bool SHOCK, bool LGL>
 __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, real, SHOCK>::minw))
     k_volume(const View<real> *views, const int *blk_start, int nreq, View<real> single) {
   using S = Sz<N>;
@@ -807,7 +823,9 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1;
+      const int end = (f & 1) ? n - 1 : 0;  // the only node with nonzero l-hat at Gauss-Lobatto nodes
       if (d < 2) {
+        if (LGL && (d == 0 ? i : j) != end) continue;
         const real lh = (f & 1) ? sb.lhp[d == 0 ? i : j] : sb.lhm[d == 0 ? i : j];
 #pragma unroll
         for (int m = 0; m < npt; ++m) {
@@ -829,6 +847,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
 #pragma unroll
         for (int m = 0; m < npt; ++m) {
           const int km = k0 + m * kstep;
+          if (LGL && km != end) continue;
           const real lh = (f & 1) ? sb.lhp[km] : sb.lhm[km];
 #pragma unroll
           for (int dd = 0; dd < 3; ++dd) {
@@ -912,17 +931,27 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
         for (int u = 0; u < L::fpu; ++u)
 #pragma unroll
           for (int s = 0; s < 12; ++s) gt[u][s] = real(0);
+        if constexpr (LGL) {
+          // Gauss-Lobatto: the trace is the end node of the line
 #pragma unroll
-        for (int l = 0; l < n; ++l) {
-          real w[L::fpu];
+          for (int u = 0; u < L::fpu; ++u) {
+            const real *row = sm + L::G + base + ((s0 + u) != 0 ? (n - 1) * stride : 0);
 #pragma unroll
-          for (int u = 0; u < L::fpu; ++u) w[u] = lw[u][l];
-          const real *row = sm + L::G + base + l * stride;
+            for (int s = 0; s < 12; ++s) gt[u][s] = row[s * L::gsz];
+          }
+        } else {
 #pragma unroll
-          for (int s = 0; s < 12; ++s) {
-            const real gv = row[s * L::gsz];
+          for (int l = 0; l < n; ++l) {
+            real w[L::fpu];
 #pragma unroll
-            for (int u = 0; u < L::fpu; ++u) gt[u][s] += w[u] * gv;
+            for (int u = 0; u < L::fpu; ++u) w[u] = lw[u][l];
+            const real *row = sm + L::G + base + l * stride;
+#pragma unroll
+            for (int s = 0; s < 12; ++s) {
+              const real gv = row[s * L::gsz];
+#pragma unroll
+              for (int u = 0; u < L::fpu; ++u) gt[u][s] += w[u] * gv;
+            }
           }
         }
 #pragma unroll
@@ -1011,7 +1040,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
 // blending factors and hands a workgroup with a blended element to the blend
 // pass; SH = 2 (the blend pass) adds the FV subcell operator.
 // ---------------------------------------------------------------------------
-template <int N, typename real, int SH>
+template <int N, typename real, int SH, bool LGL>
 __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk, const int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
@@ -1115,7 +1144,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
       {
         int base, stride;
         Pad<n>::face_line(f, pq, base, stride);
-        prolong_state<n>(su, (f & 1) ? sb.lp : sb.lm, base, stride, Uo);
+        face_state<n, LGL>(su, (f & 1) ? sb.lp : sb.lm, base, stride, f & 1, Uo);
       }
 #pragma unroll
       for (int s = 0; s < 5; ++s) Un[s] = (tr + s * Ef)[in];
@@ -1211,6 +1240,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1;
+      // at Gauss-Lobatto nodes l-hat vanishes off the end node of the line
       const real lh = (f & 1) ? sb.lhp[lf[d]] : sb.lhm[lf[d]];
 #pragma unroll
       for (int c = 0; c < 5; ++c) V[c] += sS[le][c][f * n2 + pqf[d]] * lh;
@@ -1260,7 +1290,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         int base, stride;
         Pad<n>::face_line(f, pq, base, stride);
         real t[5];
-        prolong_state<n>(su, (f & 1) ? sb.lp : sb.lm, base, stride, t);
+        face_state<n, LGL>(su, (f & 1) ? sb.lp : sb.lm, base, stride, f & 1, t);
 #pragma unroll
         for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
       }
@@ -1271,18 +1301,21 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
 
 // Surface sweep: SH = 0 without shock capturing; SH = 1 with it, for the
 // workgroups without a blended element (the others are listed for k_blend).
-template <int N, typename real, int SH>
+template <int N, typename real, int SH, bool LGL>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
                                                                           int nreq, View<real> single, int mode) {
   int lblk;
   const View<real> v = select_view(views, blk_start, nreq, single, lblk);
-  surface_body<N, real, SH>(v, lblk, mode);
+  surface_body<N, real, SH, LGL>(v, lblk, mode);
 }
 
 // Blend pass: the surface sweep with the FV subcell blend, for the workgroups
 // that k_surface<SH = 1> listed, request by request; a fixed grid strides over
-// each list.
-template <int N, typename real>
+// each list.  The compiler hoists the body's invariant work out of the loop
+// and takes up to 256 VGPRs (one workgroup per SIMD); an out-of-line body
+// needs half, but its call stack made every launch, empty ones included,
+// 8 us slower, and the pass rarely has more than a few workgroups.
+template <int N, typename real, bool LGL>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_blend(const View<real> *views, int nreq,
                                                                         View<real> single, int mode) {
   const int nr = nreq == 0 ? 1 : nreq;
@@ -1290,7 +1323,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_blend(const Vie
     const View<real> v = nreq == 0 ? single : rebase(views[r], single.base);
     const int cnt = v.bcnt[v.bpar];
     for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
-      surface_body<N, real, 2>(v, v.blist[idx], mode);
+      surface_body<N, real, 2, LGL>(v, v.blist[idx], mode);
       __syncthreads();  // LDS is reused by the next listed workgroup
     }
   }
@@ -1435,37 +1468,37 @@ int block_threads(int N) {
 // workgroups of the blend pass: one per CU
 constexpr int kBlendBlocks = 256;
 
-template <int N, typename real>
-static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const int *blk_start, int nreq, int blocks,
+template <int N, typename real, bool LGL>
+static hipError_t launch_nl(Kernel k, int mode, const View<real> *views, const int *blk_start, int nreq, int blocks,
                            const View<real> &v0, hipStream_t st) {
   dim3 grid(blocks), block(Sz<N>::threads);
   switch (k) {
     case K_TRACE:
-      k_trace<N, real><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
+      k_trace<N, real, LGL><<<grid, block, 0, st>>>(views, blk_start, nreq, v0);
       break;
     case K_LIFT:
       // volume sweep: indicator (shock capturing), lifting (viscous), VolInt
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          k_volume<N, real, true><<<grid, (VolLds<N, real, true>::threads), 0, st>>>(views, blk_start, nreq, v0);
+          k_volume<N, real, true, LGL><<<grid, (VolLds<N, real, true>::threads), 0, st>>>(views, blk_start, nreq, v0);
         } else {
           return hipErrorInvalidValue;
         }
       } else {
-        k_volume<N, real, false><<<grid, (VolLds<N, real, false>::threads), 0, st>>>(views, blk_start, nreq, v0);
+        k_volume<N, real, false, LGL><<<grid, (VolLds<N, real, false>::threads), 0, st>>>(views, blk_start, nreq, v0);
       }
       break;
     case K_RHS:
       // surface sweep (after a volume sweep), or the one-sweep Euler operator
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          k_surface<N, real, 1><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
-          k_blend<N, real><<<std::min(blocks, kBlendBlocks), block, 0, st>>>(views, nreq, v0, mode);
+          k_surface<N, real, 1, LGL><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          k_blend<N, real, LGL><<<std::min(blocks, kBlendBlocks), block, 0, st>>>(views, nreq, v0, mode);
         } else {
           return hipErrorInvalidValue;
         }
       } else if (v0.viscous) {
-        k_surface<N, real, 0><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        k_surface<N, real, 0, LGL><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       } else {
         k_rhs<N, real><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       }
@@ -1473,6 +1506,14 @@ static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const in
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Gauss-Lobatto nodes take their own instantiations (face values are end nodes)
+template <int N, typename real>
+static hipError_t launch_n(Kernel k, int mode, const View<real> *views, const int *blk_start, int nreq, int blocks,
+                           const View<real> &v0, hipStream_t st) {
+  return v0.lgl ? launch_nl<N, real, true>(k, mode, views, blk_start, nreq, blocks, v0, st)
+                : launch_nl<N, real, false>(k, mode, views, blk_start, nreq, blocks, v0, st);
 }
 
 template <typename real>

@@ -425,12 +425,12 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
 
 // one RK stage for every active request
 dg_status tick(dg_server *sv) {
-  // one group per kernel set: degree, precision, shock capturing, viscosity
-  std::map<std::tuple<int, int, int, int>, std::vector<Request *>> groups;
+  // one group per kernel set: degree, precision, shock capturing, viscosity, nodes
+  std::map<std::tuple<int, int, int, int, int>, std::vector<Request *>> groups;
   for (int64_t id : sv->active) {
     Request &r = *sv->reqs[id];
     if (r.retiring || r.step >= r.n_steps) continue;
-    groups[{r.p.N, r.p.precision, r.p.shock_capturing, r.p.viscous}].push_back(&r);
+    groups[{r.p.N, r.p.precision, r.p.shock_capturing, r.p.viscous, r.p.nodes}].push_back(&r);
   }
   for (auto &kv : groups) {
     const int N = std::get<0>(kv.first);

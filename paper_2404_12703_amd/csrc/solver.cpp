@@ -134,6 +134,7 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.riemann = p.riemann;
   v.source = p.source;
   v.shock = p.shock_capturing;
+  v.lgl = p.nodes == 1;
   {
     const char *env = std::getenv("DG_XCD_REMAP");
     v.remap = env ? std::atoi(env) : 0;
