@@ -38,7 +38,11 @@ using namespace dg;
 
 namespace {
 
-constexpr int kDescSlots = 16;  // ring of descriptor uploads in flight
+constexpr int kDescSlots = 64;  // ring of descriptor uploads in flight
+// Streams the groups of a tick run on, in turn: groups hold disjoint requests,
+// so small batches of different degrees overlap instead of queueing behind
+// each other's tails.  Each tick forks from the server's stream and joins it.
+constexpr int kGroupStreams = 3;
 constexpr int kPrepAhead = 16;  // requests at the head of the queue prepared ahead of admission
 constexpr size_t kGeoCacheBytes = size_t(4) << 30;  // host memory of the geometry cache
 enum { PREP_WAITING = 0, PREP_RUNNING = 1, PREP_READY = 2, PREP_FAILED = 3 };
@@ -210,6 +214,8 @@ struct dg_server {
   char *desc_host[kDescSlots] = {};
   hipEvent_t desc_ev[kDescSlots] = {};
   int desc_next = 0;
+  hipStream_t gst[kGroupStreams] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kGroupStreams] = {};
   int *flags_dev = nullptr;
   // reqs and queue are shared with the preparation thread: changed under prep_mu
   std::map<int64_t, std::unique_ptr<Request>> reqs;
@@ -385,11 +391,13 @@ View<real> as_offsets(View<real> v, const char *arena) {
 
 // one batched launch of kernel k over the group; descriptors go through the ring
 template <typename real>
-dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request *> &grp) {
+dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request *> &grp, hipStream_t st) {
   if (grp.empty()) return DG_OK;
   const int slot = sv->desc_next;
   sv->desc_next = (sv->desc_next + 1) % kDescSlots;
-  hipError_t e = hipEventSynchronize(sv->desc_ev[slot]);  // the upload that last used this slot is done
+  // the kernel that last read this slot is done, so its host mirror and device
+  // copy may be rewritten (that kernel may have run on another stream)
+  hipError_t e = hipEventSynchronize(sv->desc_ev[slot]);
   if (e != hipSuccess) return server_fail(sv, e, "descriptor ring");
   char *h = sv->desc_host[slot];
   View<real> *views = (View<real> *)h;
@@ -411,14 +419,14 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
   }
   blk[grp.size()] = total;
   char *d = sv->arena + slot * sv->desc_stride;
-  e = hipMemcpyAsync(d, h, sv->desc_stride, hipMemcpyHostToDevice, sv->st);
-  if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[slot], sv->st);
+  e = hipMemcpyAsync(d, h, sv->desc_stride, hipMemcpyHostToDevice, st);
   // the argument view: the group's settings (shock capturing, viscosity) and the arena
   View<real> v0 = view_of<real>(*grp[0]);
   v0.base = sv->arena;
   if (e == hipSuccess)
     e = launch<real>(k, N, 0, (const View<real> *)d, (const int *)(d + sv->max_active * view_bytes()), (int)grp.size(),
-                     total, v0, sv->st);
+                     total, v0, st);
+  if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[slot], st);
   if (e != hipSuccess) return server_fail(sv, e, "batched launch");
   return DG_OK;
 }
@@ -432,20 +440,27 @@ dg_status tick(dg_server *sv) {
     if (r.retiring || r.step >= r.n_steps) continue;
     groups[{r.p.N, r.p.precision, r.p.shock_capturing, r.p.viscous, r.p.nodes}].push_back(&r);
   }
+  if (groups.empty()) return DG_OK;
+  hipError_t e = hipEventRecord(sv->fork_ev, sv->st);
+  const int nst = std::min((int)groups.size(), kGroupStreams);
+  for (int i = 0; i < nst && e == hipSuccess; ++i) e = hipStreamWaitEvent(sv->gst[i], sv->fork_ev, 0);
+  if (e != hipSuccess) return server_fail(sv, e, "tick fork");
+  int gi = 0;
   for (auto &kv : groups) {
     const int N = std::get<0>(kv.first);
     const bool mixed = std::get<1>(kv.first) == 1;
+    hipStream_t gs = sv->gst[gi++ % kGroupStreams];
     std::vector<Request *> fresh, visc;
     for (Request *r : kv.second) {
       if (!r->traces_valid) fresh.push_back(r);
       if (r->p.viscous || r->p.shock_capturing) visc.push_back(r);
     }
     dg_status rc;
-    rc = mixed ? launch_group<float>(sv, K_TRACE, N, fresh) : launch_group<double>(sv, K_TRACE, N, fresh);
+    rc = mixed ? launch_group<float>(sv, K_TRACE, N, fresh, gs) : launch_group<double>(sv, K_TRACE, N, fresh, gs);
     if (rc) return rc;
-    rc = mixed ? launch_group<float>(sv, K_LIFT, N, visc) : launch_group<double>(sv, K_LIFT, N, visc);
+    rc = mixed ? launch_group<float>(sv, K_LIFT, N, visc, gs) : launch_group<double>(sv, K_LIFT, N, visc, gs);
     if (rc) return rc;
-    rc = mixed ? launch_group<float>(sv, K_RHS, N, kv.second) : launch_group<double>(sv, K_RHS, N, kv.second);
+    rc = mixed ? launch_group<float>(sv, K_RHS, N, kv.second, gs) : launch_group<double>(sv, K_RHS, N, kv.second, gs);
     if (rc) return rc;
     for (Request *r : kv.second) {
       r->traces_valid = true;
@@ -458,6 +473,12 @@ dg_status tick(dg_server *sv) {
       }
     }
   }
+  // join: retirement and the next tick's work follow every group's launches
+  for (int i = 0; i < nst && e == hipSuccess; ++i) {
+    e = hipEventRecord(sv->join_ev[i], sv->gst[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sv->st, sv->join_ev[i], 0);
+  }
+  if (e != hipSuccess) return server_fail(sv, e, "tick join");
   return DG_OK;
 }
 
@@ -543,6 +564,25 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->desc_ev[s], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[s], sv->st);
     if (e != hipSuccess) return fail(DG_EDEVICE, std::string("server set-up: ") + hipGetErrorString(e));
+  }
+  {
+    hipError_t e = hipEventCreateWithFlags(&sv->fork_ev, hipEventDisableTiming);
+    for (int i = 0; i < kGroupStreams && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&sv->gst[i], hipStreamNonBlocking);  // default priority
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->join_ev[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      for (int i = 0; i < kGroupStreams; ++i) {
+        if (sv->gst[i]) (void)hipStreamDestroy(sv->gst[i]);
+        if (sv->join_ev[i]) (void)hipEventDestroy(sv->join_ev[i]);
+      }
+      if (sv->fork_ev) (void)hipEventDestroy(sv->fork_ev);
+      for (int s = 0; s < kDescSlots; ++s) {
+        if (sv->desc_host[s]) (void)hipHostFree(sv->desc_host[s]);
+        if (sv->desc_ev[s]) (void)hipEventDestroy(sv->desc_ev[s]);
+      }
+      return fail(DG_EDEVICE, std::string("server streams: ") + hipGetErrorString(e));
+    }
   }
   sv->t0 = std::chrono::steady_clock::now();
   sv->prep_thread = std::thread(prep_loop, sv.get());
@@ -658,6 +698,14 @@ void dg_server_destroy(dg_server *sv) {
     if (r.done_ev) (void)hipEventDestroy(r.done_ev);
     if (r.ready) (void)hipEventDestroy(r.ready);
   }
+  for (int i = 0; i < kGroupStreams; ++i) {
+    if (sv->gst[i]) {
+      (void)hipStreamSynchronize(sv->gst[i]);
+      (void)hipStreamDestroy(sv->gst[i]);
+    }
+    if (sv->join_ev[i]) (void)hipEventDestroy(sv->join_ev[i]);
+  }
+  if (sv->fork_ev) (void)hipEventDestroy(sv->fork_ev);
   for (int s = 0; s < kDescSlots; ++s) {
     if (sv->desc_host[s]) (void)hipHostFree(sv->desc_host[s]);
     if (sv->desc_ev[s]) (void)hipEventDestroy(sv->desc_ev[s]);
