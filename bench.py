@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64, vector or matrix
 
 
 def algorithmic_bytes_per_dof(N: int, mixed: bool):
@@ -58,8 +59,9 @@ def kernel_source_hash():
 
 
 def load_traffic(name):
-    """HBM traffic per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    runs, valid only for the kernel sources they were taken on"""
+    """a committed rocprofv3 counter record (HBM bytes per launch from
+    FETCH_SIZE/WRITE_SIZE, or FP64 VALU flops per launch from SQ counters),
+    valid only for the kernel sources it was taken on"""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -156,9 +158,24 @@ def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30,
                 makespan_s=makespan, budget_GB=budget / 2 ** 30)
 
 
-def cpu_baseline(wl, seconds_budget=30.0):
+_ONE_THREAD = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle as O, workloads as W
+wl = W.tgv_workload(K={K}, N=7, steps=1)
+o = O.Oracle(wl.params, wl.mesh)
+t0 = time.perf_counter()
+o.rhs(wl.U0)
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_baseline(wl, K, seconds_budget=30.0):
     """the FP64 oracle, untuned, on the host cores: one full RK step (five
-    operator evaluations) of the same workload"""
+    operator evaluations) of the same workload; and on one thread (a child
+    process, since the thread count is fixed when the oracle loads) one
+    operator evaluation"""
+    import subprocess
     import oracle as O
     o = O.Oracle(wl.params, wl.mesh)
     dt = o.stable_dt(wl.U0)
@@ -166,8 +183,18 @@ def cpu_baseline(wl, seconds_budget=30.0):
     o.advance(wl.U0, dt, 1)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=wl.dof * 5 / el, unit="DOF*stage/s", cores=cores, kind="oracle",
-                sample=f"1 RK step (5 operator evaluations) of the full {wl.name} workload, {el:.1f} s")
+    out = dict(value=wl.dof * 5 / el, unit="DOF*stage/s", cores=cores, kind="oracle",
+               sample=f"1 RK step (5 operator evaluations) of the full {wl.name} workload, {el:.1f} s")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", _ONE_THREAD.format(root=ROOT, K=K)], env=env, capture_output=True,
+                           text=True, timeout=10 * seconds_budget)
+        el1 = float(r.stdout.strip().splitlines()[-1])
+        out["one_thread"] = dict(value=wl.dof / el1, unit="DOF*stage/s", cores=1,
+                                 sample=f"1 operator evaluation of the full {wl.name} workload, {el1:.1f} s")
+    except Exception as ex:  # reported, not fatal: the baseline is context
+        out["one_thread"] = dict(value=None, error=str(ex)[:200])
+    return out
 
 
 def main():
@@ -246,6 +273,7 @@ def main():
         names = {"lift": ("k_volume", "Lift_* + VolInt + own-side viscous face flux", vol_b),
                  "rhs": ("k_surface", "FillFlux + SurfInt + ApplyJac + LSERK update + ProlongToFace", surf_b)}
         tr = load_traffic("traffic_tgv24_n7_fp64.json")
+        va = load_traffic("valu_tgv24_n7_fp64.json")  # FP64 VALU flops per launch from SQ counters
         kern = {}
         for key, (name, what, b) in names.items():
             ms, nl = prof[key]
@@ -253,6 +281,12 @@ def main():
             kern[name] = {"computes": what, "avg_ms": t * 1e3, "launches": nl, "alg_bytes_per_dof": b,
                           "alg_GBs": b * wl.dof / t / 1e9,
                           "traffic_bytes_per_launch": (tr["kernels"][name] if tr else None)}
+            if va:
+                fl = va["kernels"][name]["fp64_flop_per_launch"]
+                kern[name].update(fp64_flop_per_launch=fl, fp64_TFLOPs=fl / t / 1e12,
+                                  fp64_frac=fl / t / 1e12 / FP64_PEAK_TFLOPS,
+                                  mfma_instr=va["kernels"][name]["mfma_f64_instr"],
+                                  lds_idx_active=va["kernels"][name]["lds_idx_active_per_busy_cycle"])
         dom = max(kern, key=lambda k: kern[k]["avg_ms"])
         kd = kern[dom]
         line["roofline"] = {"kernel": f"{dom} ({kd['computes']})", "bound": "hbm", "achieved": kd["alg_GBs"],
@@ -300,7 +334,7 @@ def main():
                           for ld in (0.5, 0.8, 1.2, None)]
         line["served"].append(served(P, W, args.serve_requests, 0, value, load=0.8, precision=1))
     if not args.no_cpu and not args.only_main:
-        line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1))
+        line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1), args.K)
     print(json.dumps(line), flush=True)
 
 
