@@ -93,6 +93,31 @@ def test_batched_blast_equals_alone_bitwise():
     assert max(blended) > 0
 
 
+def test_gauss_and_lobatto_requests_group_apart():
+    """Requests of one degree with Gauss and with Gauss-Lobatto nodes run in
+    separate groups (their kernels differ) in the same ticks; each result is
+    still the request's own solve, bitwise."""
+    import math
+    import paper_2404_12703_amd as P
+    _say("[server] N = 5 requests, Gauss and Lobatto nodes mixed")
+    wls = []
+    for i, (K, nodes) in enumerate(((3, 0), (3, 1), (4, 1), (4, 0))):
+        mesh = W.box_mesh(K, 0.0, 2 * math.pi, 5)
+        p = W.params(5, node_type=nodes, riemann=1, viscous=1, mu=1.0 / 800.0)
+        X = mesh.points(W.lgl_points(5) if nodes else W.gl_points(5))
+        wls.append(W.Workload("tgv_req", p, mesh, W.tgv_state(X, 0.1 + 0.05 * i, p["gamma"]), 4))
+    sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=8)
+    ids, dts = [], []
+    for wl in wls:
+        dts.append(_dt(wl))
+        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, wl.steps, dts[-1], 0.0))
+    sv.run(0)
+    for wl, rid, dt in zip(wls, ids, dts):
+        assert sv.poll(rid) == P.REQ_DONE
+        U, _ = sv.fetch(rid)
+        assert np.array_equal(U, _alone(wl, dt)), (wl.mesh.n_elems, wl.params["nodes"])
+
+
 def test_poisoned_request_fails_alone_and_budget_binds():
     import paper_2404_12703_amd as P
     reqs = _requests(6, 1, precision_mix=False)
