@@ -626,15 +626,15 @@ struct VolLds {
   // would spill registers.
   static constexpr bool f64 = sizeof(real) == 8;
   static constexpr int fpu = (N == 6 || (f64 && (N == 5 || N >= 9 || (N == 7 && SHOCK)))) ? 1 : 2;
-  // Nodes per thread: where a wave is one k-plane of one element (N = 7),
+  // Nodes per thread: at N = 7 and N = 5 (one element per workgroup, even n)
   // a thread of the mixed form without shock capturing takes the two nodes k
   // and k + n/2 of one column.  They share the reads along zeta, the D-hat
   // rows along xi and eta and the zeta faces of Lift_SurfInt; the workgroup
   // has half the threads, each with twice the registers.  That took 7% off
-  // the mixed sweep; in FP64 the pairs need all 256 VGPRs at two waves per
-  // SIMD and measured no faster.
+  // the mixed sweep at both degrees; in FP64 the pairs need all 256 VGPRs at
+  // two waves per SIMD and measured no faster.
   static constexpr bool plane_waves = S::n2 == 64 && S::epb == 1;
-  static constexpr int npt = (plane_waves && !SHOCK && !f64) ? 2 : 1;
+  static constexpr int npt = ((N == 7 || N == 5) && !SHOCK && !f64) ? 2 : 1;
   static constexpr int tpe = n3 / npt;  // threads per element
   static constexpr int threads = npt == 1 ? S::threads : tpe;
   static constexpr int minw = npt == 1 ? S::minw : 2;

@@ -31,28 +31,31 @@ def _run(wl, steps, dt):
     return s.state(), s.integrals()
 
 
-def test_mixed_rhs_close_to_oracle():
-    wl = W.tgv_workload(K=3, N=7, rotate=True, precision=1)
+@pytest.mark.parametrize("K,N", [(3, 7), (4, 5)])
+def test_mixed_rhs_close_to_oracle(K, N):
+    wl = W.tgv_workload(K=K, N=N, rotate=True, precision=1)
     import paper_2404_12703_amd as P
     s = P.Solver(wl.params, wl.mesh)
     s.set_state(wl.U0)
     Rm = s.rhs(0.0)
     Ro = O.Oracle(wl.params, wl.mesh).rhs(wl.U0, 0.0)
     e = rel(Rm, Ro)
-    _say(f"[mixed rhs] rel L2 vs oracle {e:.3e}")
+    _say(f"[mixed rhs] N = {N}: rel L2 vs oracle {e:.3e}")
     # FP32 rounding of the p0 ~ 71 pressure flux, differentiated: measured 6.8e-3
     assert e < 2e-2
 
 
-def test_mixed_kinetic_energy_error_after_steps():
-    """TGV, curved 4^3 mesh, N = 7, 100 steps: E_k of the mixed form within 1e-6 of FP64"""
-    wd = W.tgv_workload(K=4, N=7, precision=0)
-    wm = W.tgv_workload(K=4, N=7, precision=1)
+@pytest.mark.parametrize("K,N", [(4, 7), (5, 5)])
+def test_mixed_kinetic_energy_error_after_steps(K, N):
+    """TGV, curved mesh, 100 steps: E_k of the mixed form within 1e-6 of FP64
+    (N = 7 and 5 take the two-nodes-per-thread volume sweep)"""
+    wd = W.tgv_workload(K=K, N=N, precision=0)
+    wm = W.tgv_workload(K=K, N=N, precision=1)
     dt = O.Oracle(wd.params, wd.mesh).stable_dt(wd.U0)
     Ud, Id = _run(wd, 100, dt)
     Um, Im = _run(wm, 100, dt)
     ek = abs(Im[5] - Id[5]) / abs(Id[5])
     el2 = rel(Um, Ud)
-    _say(f"[mixed 100 steps] Ek rel err {ek:.3e}, state rel L2 {el2:.3e}")
+    _say(f"[mixed 100 steps] N = {N}: Ek rel err {ek:.3e}, state rel L2 {el2:.3e}")
     assert ek <= 1e-6
     assert el2 <= 1e-5
