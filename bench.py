@@ -268,6 +268,19 @@ def main():
     }
     if args.copy_calib:
         line["copy_kernel_GBs"] = copy_gbs
+    if not args.only_main:
+        # the same timed interval four more times: median and spread of five
+        import torch
+        vals = [value]
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance(args.steps, dt)
+            s.synchronize()
+            torch.cuda.synchronize()
+            vals.append(wl.dof * 5 * args.steps / (time.perf_counter() - t0))
+        line["repeats"] = {"n": 5, "median": float(np.median(vals)), "min": float(np.min(vals)),
+                           "max": float(np.max(vals))}
     if prof is not None:
         vol_b, surf_b = algorithmic_bytes_per_dof(N, False)
         names = {"lift": ("k_volume", "Lift_* + VolInt + own-side viscous face flux", vol_b),
