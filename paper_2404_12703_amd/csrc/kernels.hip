@@ -626,15 +626,17 @@ struct VolLds {
   // would spill registers.
   static constexpr bool f64 = sizeof(real) == 8;
   static constexpr int fpu = (N == 6 || (f64 && (N == 5 || N >= 9 || (N == 7 && SHOCK)))) ? 1 : 2;
-  // Nodes per thread: at N = 7 and N = 5 (one element per workgroup, even n)
-  // a thread of the mixed form without shock capturing takes the two nodes k
-  // and k + n/2 of one column.  They share the reads along zeta, the D-hat
-  // rows along xi and eta and the zeta faces of Lift_SurfInt; the workgroup
-  // has half the threads, each with twice the registers.  That took 7% off
-  // the mixed sweep at both degrees; in FP64 the pairs need all 256 VGPRs at
-  // two waves per SIMD and measured no faster.
+  // Nodes per thread: at N = 7 (and N = 5 in the mixed form; one element
+  // per workgroup, even n) a thread without shock capturing takes the two
+  // nodes k and k + n/2 of one column.  They share the reads along zeta, the
+  // D-hat rows along xi and eta and the zeta faces of Lift_SurfInt; the
+  // workgroup has half the threads, each with twice the registers.  That took
+  // 7% off the mixed sweep at both degrees and 1% off the FP64 sweep at N = 7,
+  // where the lifting contraction is unrolled by 4 instead of n so that its
+  // loads in flight fit 256 VGPRs (fully unrolled it spilled).
   static constexpr bool plane_waves = S::n2 == 64 && S::epb == 1;
-  static constexpr int npt = ((N == 7 || N == 5) && !SHOCK && !f64) ? 2 : 1;
+  static constexpr int npt = ((N == 7 && !SHOCK) || (N == 5 && !SHOCK && !f64)) ? 2 : 1;
+  static constexpr int lift_unroll = (npt == 2 && f64) ? 4 : S::n;
   static constexpr int tpe = n3 / npt;  // threads per element
   static constexpr int threads = npt == 1 ? S::threads : tpe;
   static constexpr int minw = npt == 1 ? S::minw : 2;
@@ -786,7 +788,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK>::threads), (VolLds<N, 
 #pragma unroll
     for (int ci = 0; ci < 3; ++ci) {
       const real *Jr = sm + L::J + 3 * ci * n3;
-#pragma unroll
+#pragma unroll L::lift_unroll
       for (int al = 0; al < n; ++al) {
         if (ci < 2) {
           const real dh = sb.Dh[(ci == 0 ? i : j) * (n + 1) + al];
