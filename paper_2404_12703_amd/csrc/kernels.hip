@@ -631,12 +631,13 @@ struct VolLds {
   // nodes k and k + n/2 of one column.  They share the reads along zeta, the
   // D-hat rows along xi and eta and the zeta faces of Lift_SurfInt; the
   // workgroup has half the threads, each with twice the registers.  That took
-  // 7% off the mixed sweep at both degrees and 1% off the FP64 sweep at N = 7,
-  // where the lifting contraction is unrolled by 4 instead of n so that its
-  // loads in flight fit 256 VGPRs (fully unrolled it spilled).
+  // 7% off the mixed sweep at both degrees and 2 to 3% off the FP64 sweep at
+  // N = 7, where the lifting contraction is unrolled by 2 instead of n: fully
+  // unrolled, its loads in flight spilled past 256 VGPRs (by 4: 216 VGPRs and
+  // slower than by 2, 176 VGPRs; not unrolled: slower again).
   static constexpr bool plane_waves = S::n2 == 64 && S::epb == 1;
   static constexpr int npt = ((N == 7 && !SHOCK) || (N == 5 && !SHOCK && !f64)) ? 2 : 1;
-  static constexpr int lift_unroll = (npt == 2 && f64) ? 4 : S::n;
+  static constexpr int lift_unroll = (npt == 2 && f64) ? 2 : S::n;
   static constexpr int tpe = n3 / npt;  // threads per element
   static constexpr int threads = npt == 1 ? S::threads : tpe;
   static constexpr int minw = npt == 1 ? S::minw : 2;
