@@ -60,14 +60,23 @@ def lib():
         L.orc_fv_volume.argtypes = [C.c_void_p, _dp, C.c_long, _dp]
         L.orc_indicator.restype = C.c_double
         L.orc_indicator.argtypes = [C.c_void_p, _dp, C.c_long]
+        L.orc_set_params2.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int]
+        L.orc_rk_scheme.restype = C.c_int
+        L.orc_rk_scheme.argtypes = [C.c_int, _dp, _dp, _dp]
+        L.orc_dissipation.restype = C.c_int
+        L.orc_dissipation.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_two_point.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_viscosity.restype = C.c_double
+        L.orc_viscosity.argtypes = [C.c_void_p, C.c_double]
         _lib = L
     return _lib
 
 
-def rk_coefficients():
-    A, B, Cc = np.zeros(5), np.zeros(5), np.zeros(5)
-    lib().orc_rk_coefficients(A, B, Cc)
-    return A, B, Cc
+def rk_coefficients(scheme: int = 0):
+    """(A, B, c) of the low-storage scheme: 0 five stages, 1 fourteen"""
+    A, B, Cc = np.zeros(14), np.zeros(14), np.zeros(14)
+    ns = lib().orc_rk_scheme(int(scheme), A, B, Cc)
+    return A[:ns].copy(), B[:ns].copy(), Cc[:ns].copy()
 
 
 class Oracle:
@@ -94,6 +103,9 @@ class Oracle:
                              int(p["viscous"]), int(p["source"]), int(p.get("shock_capturing", 0)),
                              p.get("alpha_max", 1.0), p.get("alpha_min", 0.001), p.get("ind_a", 0.5),
                              p.get("ind_c", 1.8), p.get("ind_s", np.log(9999.0)))
+        lib().orc_set_params2(self.h, int(p.get("alpha_smooth", 0)), int(p.get("volume_flux", 0)),
+                              int(p.get("viscosity", 0)), float(p.get("T_ref", 1.0)),
+                              int(p.get("time_scheme", 0)))
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -174,3 +186,20 @@ class Oracle:
 
     def indicator(self, U, e):
         return lib().orc_indicator(self.h, self._state(U), int(e))
+
+    def dissipation(self, U):
+        """(eps_S, eps_D) of Sec. 5.2 from the lifted gradients of U"""
+        out = np.zeros(2)
+        if lib().orc_dissipation(self.h, self._state(U), out) != 0:
+            raise ValueError("dissipation rates need the viscous operator")
+        return out
+
+    def two_point(self, which, UL, UR, m):
+        F = np.zeros(5)
+        lib().orc_two_point(self.h, int(which), np.ascontiguousarray(UL, dtype=np.float64),
+                            np.ascontiguousarray(UR, dtype=np.float64),
+                            np.ascontiguousarray(m, dtype=np.float64), F)
+        return F
+
+    def viscosity(self, T):
+        return lib().orc_viscosity(self.h, float(T))

@@ -61,6 +61,12 @@ typedef struct orc {
   double gamma, R, Pr, mu;
   int riemann, viscous, source, shock;
   double alpha_max, alpha_min, ind_a, ind_c, ind_s;
+  int alpha_smooth;     /* 1: raise alpha to half the largest face neighbour's value */
+  int volume_flux;      /* 0 standard weak form; 1 split form, Pirozzoli's two-point flux;
+                           2 split form with the mean of the two fluxes (a pin only) */
+  int visc_law;         /* 0 constant mu; 1 Sutherland's law, mu = mu(T_ref) */
+  int rk_scheme;        /* 0 five-stage, 1 fourteen-stage low-storage RK */
+  double T_ref;         /* Sutherland reference temperature */
   double *alpha;        /* [E] last blending factors */
   int alpha_frozen;     /* 1: use alpha[] as given instead of the indicator */
   double *Vinv;         /* [n][n] inverse orthonormal-Legendre Vandermonde */
@@ -292,11 +298,22 @@ static void flux_adv(const double *U, const double *P, int d, double *F) {
   F[4] = (U[4] + P[4]) * ud;
 }
 
+/* Sec. 2.1, Eq. sutherland: the dynamic viscosity at temperature T.  The
+ * paper writes Sutherland's law normalised by the reference temperature,
+ * mu = mu_ref 1.4042 (T/T_ref)^(3/2) / (T/T_ref + 0.4042); without it the
+ * viscosity is the constant mu. */
+static double viscosity(const orc *o, double T) {
+  if (o->visc_law == 0) return o->mu;
+  double th = T / o->T_ref;
+  return o->mu * 1.4042 * th * sqrt(th) / (th + 0.4042);
+}
+
 /* Sec. 2.1: viscous flux in direction d from the primitives and the lifted
  * gradients g[dd][var] (var: u,v,w,T).  tau = mu(grad u + grad u^T - 2/3 div u I),
- * q = -lambda grad T, lambda = gamma R mu / ((gamma-1) Pr).  Enters as F - Fv. */
+ * q = -lambda grad T, lambda = gamma R mu / ((gamma-1) Pr), mu = mu(T).
+ * Enters as F - Fv. */
 static void flux_visc(const orc *o, const double *P, const double *g, int d, double *F) {
-  double mu = o->mu;
+  double mu = viscosity(o, P[5]);
   double lam = o->gamma * o->R * mu / ((o->gamma - 1.0) * o->Pr);
   double divu = g[0 * NL + 0] + g[1 * NL + 1] + g[2 * NL + 2];
   double tau[3];
@@ -388,6 +405,45 @@ static void riemann(const orc *o, int which, const double *UL, const double *PL,
                     const double *PR, const double *nv, double *F) {
   if (which == 1) riemann_roe(o, UL, PL, UR, PR, nv, F);
   else riemann_llf(o, UL, PL, UR, PR, nv, F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.2 "Nonlinear Stability": two-point volume fluxes of the split      */
+/* form along an unnormalised direction m (in the volume integral, the mean  */
+/* of the two nodes' contravariant metric vectors).  Both are consistent:    */
+/* F#(U, U; m) = F(U).m, and symmetric in their two states.                  */
+/* ------------------------------------------------------------------------ */
+
+/* Pirozzoli's kinetic-energy-preserving flux: arithmetic means of density,
+ * velocity, pressure and specific total enthalpy H = (rho e + p)/rho; the
+ * mass flux is mean(rho) mean(u).m, momentum and energy are carried by it. */
+static void two_point_kep(const double *UL, const double *PL, const double *UR, const double *PR,
+                          const double *m, double *F) {
+  double rho = 0.5 * (PL[0] + PR[0]);
+  double u[3];
+  for (int d = 0; d < 3; ++d) u[d] = 0.5 * (PL[1 + d] + PR[1 + d]);
+  double p = 0.5 * (PL[4] + PR[4]);
+  double H = 0.5 * ((UL[4] + PL[4]) / PL[0] + (UR[4] + PR[4]) / PR[0]);
+  double mf = rho * (u[0] * m[0] + u[1] * m[1] + u[2] * m[2]);
+  F[0] = mf;
+  for (int d = 0; d < 3; ++d) F[1 + d] = mf * u[d] + p * m[d];
+  F[4] = mf * H;
+}
+
+/* the mean of the two states' fluxes along m; with it the split form is the
+ * standard DG operator on meshes with constant metric terms */
+static void two_point_mean(const double *UL, const double *PL, const double *UR, const double *PR,
+                           const double *m, double *F) {
+  double FL[NV], FR[NV];
+  flux_normal(UL, PL, m, FL);
+  flux_normal(UR, PR, m, FR);
+  for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]);
+}
+
+static void two_point(const orc *o, const double *UL, const double *PL, const double *UR,
+                      const double *PR, const double *m, double *F) {
+  if (o->volume_flux == 2) two_point_mean(UL, PL, UR, PR, m, F);
+  else two_point_kep(UL, PL, UR, PR, m, F);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -657,6 +713,7 @@ orc *orc_create(int N, int node_type, int ngeo, long E, const double *x_geo, con
   o->gamma = 1.4; o->R = 1.0; o->Pr = 0.72; o->mu = 0.0;
   o->riemann = 0; o->viscous = 0; o->source = 0; o->shock = 0;
   o->alpha_max = 1.0; o->alpha_min = 0.001; o->ind_a = 0.5; o->ind_c = 1.8; o->ind_s = log(9999.0);
+  o->alpha_smooth = 0; o->volume_flux = 0; o->visc_law = 0; o->T_ref = 1.0; o->rk_scheme = 0;
   build_basis(o);
   build_metrics(o, x_geo);
   int rc = match_faces(o, nbr_elem, nbr_face);
@@ -690,6 +747,16 @@ void orc_destroy(orc *o) {
                   o->faceF, o->liftF, o->Vadv, o->Vvis, o->Vfv};
   for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
   free(o);
+}
+
+/* the switches added to the standard scheme: alpha smoothing, split-form
+ * volume flux, Sutherland's law (reference temperature T_ref), RK scheme */
+void orc_set_params2(orc *o, int alpha_smooth, int volume_flux, int visc_law, double T_ref, int rk_scheme) {
+  o->alpha_smooth = alpha_smooth;
+  o->volume_flux = volume_flux;
+  o->visc_law = visc_law;
+  o->T_ref = T_ref;
+  o->rk_scheme = rk_scheme;
 }
 
 void orc_set_params(orc *o, double gamma, double R, double Pr, double mu, int riemann, int viscous,
@@ -956,8 +1023,11 @@ int orc_rhs(orc *o, const double *Usoa, double t, double *Utsoa) {
     }
 
   /* blending factors (Sec. 2.3), one per element: the indicator value of the
-   * element, raised to half the largest value among its face neighbours so
-   * that elements about to be reached by a shock are already blended */
+   * element, an operator local to the element.  With alpha_smooth (outside
+   * the paper: Hennemann's neighbour smoothing) the value is raised to half
+   * the largest value among its face neighbours, so that elements about to
+   * be reached by a shock are already blended; values below alpha_min then
+   * drop to zero and alpha_max caps the result. */
   if (o->shock && !o->alpha_frozen) {
     double *raw = ALLOC(double, E);
 #pragma omp parallel for schedule(static)
@@ -965,17 +1035,30 @@ int orc_rhs(orc *o, const double *Usoa, double t, double *Utsoa) {
 #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; ++e) {
       double a = raw[e];
-      for (int f = 0; f < 6; ++f) a = fmax(a, 0.5 * raw[o->nbr[e * 6 + f]]);
-      o->alpha[e] = fmin(a, o->alpha_max);
+      if (o->alpha_smooth) {
+        for (int f = 0; f < 6; ++f) a = fmax(a, 0.5 * raw[o->nbr[e * 6 + f]]);
+        if (a < o->alpha_min) a = 0.0;
+        a = fmin(a, o->alpha_max);
+      }
+      o->alpha[e] = a;
     }
     free(raw);
   }
 
   /* VolInt: contravariant fluxes F^i = Ja^i . (F_adv - F_v) at every node, then
-   * sum_alpha F^1_{alpha jk} D-hat_{i alpha} + ... (Eq. dgsem) */
+   * sum_alpha F^1_{alpha jk} D-hat_{i alpha} + ... (Eq. dgsem).
+   * Split form (Sec. 2.2 "Nonlinear Stability", Gauss-Lobatto nodes): the
+   * advective part becomes sum_alpha (2 D - W^-1 B)_{i alpha} F#^1(U_ijk, U_alpha jk)
+   * + ..., the strong-form two-point volume term with the boundary values of
+   * the strong form's surface correction folded in, so that the weak form's
+   * surface integral of f* below completes it.  On these nodes the summation-
+   * by-parts property W D + D^T W = B gives 2 D - W^-1 B = D + D-hat.  F#^1 is
+   * taken along the mean of the two nodes' metric vectors Ja^1.  The viscous
+   * part keeps the weak form. */
 #pragma omp parallel for schedule(static)
   for (long e = 0; e < E; ++e) {
     int blend = o->shock && o->alpha[e] > 0.0;
+    int split = o->volume_flux != 0;
     double *Vt = o->V + e * n3 * NV;
     double *Va = o->Vadv + e * n3 * NV, *Vv = o->Vvis + e * n3 * NV;
     for (int a = 0; a < n3 * NV; ++a) { Vt[a] = 0.0; Va[a] = 0.0; Vv[a] = 0.0; }
@@ -1019,15 +1102,27 @@ int orc_rhs(orc *o, const double *Usoa, double t, double *Utsoa) {
               else src = nidx(n, i, j, al);
               double Dh = o->Dhat[ijk[ci] * n + al];
               for (int v = 0; v < NV; ++v) {
-                if (!blend) Vt[node * NV + v] += Dh * Fc[(src * 3 + ci) * NV + v];
+                if (!blend && !split) Vt[node * NV + v] += Dh * Fc[(src * 3 + ci) * NV + v];
                 else {
-                  Va[node * NV + v] += Dh * Fa[(src * 3 + ci) * NV + v];
+                  if (!split) Va[node * NV + v] += Dh * Fa[(src * 3 + ci) * NV + v];
                   Vv[node * NV + v] -= Dh * Fv[(src * 3 + ci) * NV + v];
                 }
+              }
+              if (split) {
+                double Ds = o->D[ijk[ci] * n + al] + Dh;
+                const double *J1 = o->Ja + (e * n3 + node) * 9 + ci * 3;
+                const double *J2 = o->Ja + (e * n3 + src) * 9 + ci * 3;
+                double m[3] = {0.5 * (J1[0] + J2[0]), 0.5 * (J1[1] + J2[1]), 0.5 * (J1[2] + J2[2])};
+                double Fs[NV];
+                two_point(o, o->Ui + (e * n3 + node) * NV, o->prim + (e * n3 + node) * 6,
+                          o->Ui + (e * n3 + src) * NV, o->prim + (e * n3 + src) * 6, m, Fs);
+                for (int v = 0; v < NV; ++v) Va[node * NV + v] += Ds * Fs[v];
               }
             }
         }
     free(Fc); free(Fa); free(Fv);
+    if (split && !blend)
+      for (int a = 0; a < n3 * NV; ++a) Vt[a] = Va[a] + Vv[a];
     if (blend) {
       /* (1 - alpha) V_DG,adv + alpha V_FV + V_DG,visc */
       double al = o->alpha[e];
@@ -1089,22 +1184,55 @@ static const double RK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.
 static const double RK_C[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
                                2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
+/* The fourteen-stage fourth-order 2N-storage scheme of Niegemann, Diehl and
+ * Busch (2012), the paper's choice for its application runs (Sec. 2.2 "Time
+ * integration"): its stability region is stretched along the imaginary axis
+ * for convection-dominated problems.  Published 16-digit coefficients. */
+static const double RK14_A[14] = {0.0, -0.7188012108672410, -0.7785331173421570, -0.0053282796654044,
+                                  -0.8552979934029281, -3.9564138245774565, -1.5780575380587385,
+                                  -2.0837094552574054, -0.7483334182761610, -0.7032861106563359,
+                                  0.0013917096117681, -0.0932075369637460, -0.9514200470875948,
+                                  -7.1151571693922548};
+static const double RK14_B[14] = {0.0367762454319673, 0.3136296607553959, 0.1531848691869027, 0.0030097086818182,
+                                  0.3326293790646110, 0.2440251405350864, 0.3718879239592277, 0.6204126221582444,
+                                  0.1524043173028741, 0.0760894927419266, 0.0077604214040978, 0.0024647284755382,
+                                  0.0780348340049386, 5.5059777270269628};
+static const double RK14_C[14] = {0.0, 0.0367762454319673, 0.1249685262725025, 0.2446177702277698,
+                                  0.2476149531070420, 0.2969311120382472, 0.3978149645802642, 0.5270854589440328,
+                                  0.6981269994175695, 0.8190890835352128, 0.8527059887098624, 0.8604711817462826,
+                                  0.8627060376969976, 0.8734213127600976};
+
 void orc_rk_coefficients(double *A, double *B, double *C) {
   for (int s = 0; s < 5; ++s) { A[s] = RK_A[s]; B[s] = RK_B[s]; C[s] = RK_C[s]; }
 }
 
-/* advance U (state layout [var][elem][node]) by nsteps steps of size dt */
+/* coefficients of scheme 0 (five stages) or 1 (fourteen); returns the stage count */
+int orc_rk_scheme(int scheme, double *A, double *B, double *C) {
+  int ns = scheme == 1 ? 14 : 5;
+  for (int s = 0; s < ns; ++s) {
+    A[s] = scheme == 1 ? RK14_A[s] : RK_A[s];
+    B[s] = scheme == 1 ? RK14_B[s] : RK_B[s];
+    C[s] = scheme == 1 ? RK14_C[s] : RK_C[s];
+  }
+  return ns;
+}
+
+/* advance U (state layout [var][elem][node]) by nsteps steps of size dt with
+ * the low-storage scheme the parameters select: per stage s,
+ * du = A_s du + dt R(U, t + c_s dt), U = U + B_s du (A_1 = 0) */
 int orc_advance(orc *o, double *U, double t0, double dt, int nsteps) {
   long tot = (long)NV * o->E * o->n3;
   double *du = ALLOC(double, tot), *R = ALLOC(double, tot);
+  double A[14], B[14], Cc[14];
+  int ns = orc_rk_scheme(o->rk_scheme, A, B, Cc);
   double t = t0;
   for (int st = 0; st < nsteps; ++st) {
-    for (int s = 0; s < 5; ++s) {
-      orc_rhs(o, U, t + RK_C[s] * dt, R);
+    for (int s = 0; s < ns; ++s) {
+      orc_rhs(o, U, t + Cc[s] * dt, R);
 #pragma omp parallel for schedule(static)
       for (long a = 0; a < tot; ++a) {
-        du[a] = RK_A[s] * du[a] + dt * R[a];
-        U[a] = U[a] + RK_B[s] * du[a];
+        du[a] = A[s] * du[a] + dt * R[a];
+        U[a] = U[a] + B[s] * du[a];
       }
     }
     t = t0 + (st + 1) * dt;
@@ -1168,7 +1296,7 @@ double orc_stable_dt(const orc *o, const double *U, double cfl, double dfl) {
       double t1 = cfl * 2.0 / ((2.0 * N + 1.0) * lam);
       if (t1 < dta) dta = t1;
       if (o->viscous && o->mu > 0.0) {
-        double nu = fmax(4.0 / 3.0, g / o->Pr) * o->mu / P[0];
+        double nu = fmax(4.0 / 3.0, g / o->Pr) * viscosity(o, P[5]) / P[0];
         double t2 = dfl * 4.0 / (pow(N + 1.0, 4) * nu * vis);
         if (t2 < dtv) dtv = t2;
       }
@@ -1242,3 +1370,50 @@ double orc_indicator(orc *o, const double *Usoa, long e) {
   }
   return indicator_alpha(o, e);
 }
+
+/* Sec. 5.2 dissipation rates from the lifted gradients g of an evaluation of
+ * the operator on U: out[0] = (1/|Omega|) sum w J mu(T) omega.omega and
+ * out[1] = (4/(3 |Omega|)) sum w J mu(T) (div u)^2, omega = curl u.  With
+ * rho0 = U0 = L = 1 these are the paper's solenoidal and dilatational rates
+ * (its mu(T)/(mu0 Re) is mu(T)).  Needs the viscous operator (returns -1
+ * otherwise). */
+int orc_dissipation(orc *o, const double *Usoa, double *out) {
+  if (!o->viscous) return -1;
+  int n = o->n, n3 = o->n3;
+  long E = o->E, tot = (long)NV * E * n3;
+  double *R = ALLOC(double, tot);
+  orc_rhs(o, Usoa, 0.0, R);
+  free(R);
+  double sS = 0.0, sD = 0.0, vol = 0.0;
+  for (long e = 0; e < E; ++e)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          int a = nidx(n, i, j, k);
+          double wJ = o->w[i] * o->w[j] * o->w[k] * o->J[e * n3 + a];
+          const double *g = o->G + (e * n3 + a) * 3 * NL; /* g[d*NL + v] = d(prim v)/dx_d */
+          double mu = viscosity(o, o->prim[(e * n3 + a) * 6 + 5]);
+          double wx = g[1 * NL + 2] - g[2 * NL + 1];  /* dw/dy - dv/dz */
+          double wy = g[2 * NL + 0] - g[0 * NL + 2];  /* du/dz - dw/dx */
+          double wz = g[0 * NL + 1] - g[1 * NL + 0];  /* dv/dx - du/dy */
+          double dv = g[0 * NL + 0] + g[1 * NL + 1] + g[2 * NL + 2];
+          sS += wJ * mu * (wx * wx + wy * wy + wz * wz);
+          sD += wJ * mu * dv * dv;
+          vol += wJ;
+        }
+  out[0] = sS / vol;
+  out[1] = 4.0 / 3.0 * sD / vol;
+  return 0;
+}
+
+/* single-point two-point volume flux along m, for the pins */
+void orc_two_point(orc *o, int which, const double *UL, const double *UR, const double *m, double *F) {
+  double PL[6], PR[6];
+  cons_to_prim(o, UL, PL);
+  cons_to_prim(o, UR, PR);
+  if (which == 2) two_point_mean(UL, PL, UR, PR, m, F);
+  else two_point_kep(UL, PL, UR, PR, m, F);
+}
+
+/* viscosity at temperature T under the current law, for the pins */
+double orc_viscosity(const orc *o, double T) { return viscosity(o, T); }

@@ -1,5 +1,6 @@
-"""Pins of the oracle's Riemann solvers (FillFlux, App. A) and of the
-five-stage low-storage Runge-Kutta scheme (Sec. 2.2 Time integration)."""
+"""Pins of the oracle's Riemann solvers (FillFlux, App. A) and of the two
+low-storage Runge-Kutta schemes (Sec. 2.2 Time integration): Carpenter and
+Kennedy's five stages and Niegemann, Diehl and Busch's fourteen."""
 import json
 import os
 
@@ -110,9 +111,9 @@ def test_roe_is_upwind_for_supersonic_flow():
     assert np.allclose(o.riemann(1, VL, VR, n), _flux_n(VR, n), atol=1e-12, rtol=1e-12)
 
 
-def _butcher():
-    A, B, C = O.rk_coefficients()
-    s = 5
+def _butcher(scheme=0):
+    A, B, C = O.rk_coefficients(scheme)
+    s = len(A)
     a = np.zeros((s, s))
     b = np.zeros(s)
     # du_r = sum_{j<=r} (prod_{m=j+1}^{r} A_m) k_j ;  U_r = U_0 + sum_{r'<=r} B_r' du_r'
@@ -147,3 +148,40 @@ def test_lserk_temporal_convergence_order_four():
         errs.append(np.abs(o.advance(wl.U0, T / ns, ns) - ref).max())
     eoc = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert eoc.min() > 3.7, eoc
+
+
+def test_fourteen_stage_scheme_order_conditions():
+    """the 2N-storage coefficients of the fourteen-stage scheme, turned into a
+    Butcher tableau, meet the eight fourth-order conditions (to the 16 digits
+    the coefficients are published with) and their stage times are the row sums"""
+    a, b, C = _butcher(1)
+    assert len(b) == 14
+    c = a.sum(axis=1)
+    assert np.abs(c - C).max() < 1e-14
+    conds = [b.sum(), b @ c, b @ c ** 2, b @ (a @ c), b @ c ** 3, b @ (c * (a @ c)),
+             b @ (a @ c ** 2), b @ (a @ (a @ c))]
+    assert np.allclose(conds, GOLD["lserk45_order_conditions"]["value"], atol=1e-13, rtol=0)
+
+
+def test_fourteen_stage_temporal_convergence_order_four():
+    wl = W.mms_workload(K=2, N=3)
+    p = dict(wl.params, time_scheme=1)
+    o = O.Oracle(p, wl.mesh)
+    T = 0.8
+    ref = o.advance(wl.U0, T / 256, 256)
+    errs = [np.abs(o.advance(wl.U0, T / ns, ns) - ref).max() for ns in (8, 16, 32)]
+    eoc = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert eoc.min() > 3.6, eoc
+
+
+def test_fourteen_stage_scheme_is_stable_at_its_larger_step():
+    """the scheme's stability region is about 3.8 times longer on the imaginary
+    axis; at 3 times the five-stage step of the manufactured solution it still
+    converges to the same solution"""
+    wl = W.mms_workload(K=2, N=3)
+    o5 = O.Oracle(wl.params, wl.mesh)
+    o14 = O.Oracle(dict(wl.params, time_scheme=1), wl.mesh)
+    dt = o5.stable_dt(wl.U0, 0.9, 0.9)
+    U5 = o5.advance(wl.U0, dt, 30)
+    U14 = o14.advance(wl.U0, 3 * dt, 10)
+    assert np.abs(U14 - U5).max() < 1e-6 * np.abs(U5).max()

@@ -348,11 +348,17 @@ def random_smooth_state(X, seed, gamma, period):
 
 def params(N, node_type=0, riemann=0, viscous=1, source=0, shock=0, gamma=1.4, R=1.0, Pr=0.72,
            mu=1e-3, precision=0, alpha_max=1.0, alpha_min=0.001, ind_a=0.5, ind_c=1.8,
-           ind_s=math.log(9999.0), check_finite=0):
+           ind_s=math.log(9999.0), check_finite=0, alpha_smooth=0, volume_flux=0, viscosity=0,
+           T_ref=1.0, time_scheme=0, p_ref=0.0):
+    """volume_flux: 0 standard weak form, 1 split form with Pirozzoli's two-point
+    flux (Gauss-Lobatto nodes); viscosity: 0 constant mu, 1 Sutherland's law with
+    mu = mu(T_ref); time_scheme: 0 five-stage, 1 fourteen-stage low-storage RK;
+    p_ref: background pressure the mixed form subtracts in its FP32 fluxes"""
     return dict(N=N, nodes=node_type, riemann=riemann, viscous=viscous, source=source,
                 shock_capturing=shock, gamma=gamma, R=R, Pr=Pr, mu=mu, precision=precision,
                 alpha_max=alpha_max, alpha_min=alpha_min, ind_a=ind_a, ind_c=ind_c, ind_s=ind_s,
-                check_finite=check_finite)
+                check_finite=check_finite, alpha_smooth=alpha_smooth, volume_flux=volume_flux,
+                viscosity=viscosity, T_ref=T_ref, time_scheme=time_scheme, p_ref=p_ref)
 
 
 @dataclass
@@ -385,6 +391,24 @@ def tgv_workload(K=24, N=7, steps=100, Ma=0.1, Re=1600.0, curved=True, seed=0, p
     p = params(N, node_type=0, riemann=riemann, viscous=1, source=0, mu=1.0 / Re, precision=precision)
     X = mesh.points(gl_points(N))
     return Workload("tgv", p, mesh, tgv_state(X, Ma, p["gamma"]), steps, extra=dict(Ma=Ma, Re=Re))
+
+
+def compressible_tgv_workload(K=16, N=7, steps=100, Ma=1.25, Re=1600.0, curved=False, seed=0,
+                              rotate=False, alpha_max=1.0):
+    """the supersonic Taylor-Green vortex: [0,2pi]^3, K^3 elements, Gauss-Lobatto
+    nodes, Version II at Ma = 1.25, Re = 1600, Sutherland's law with T_ref = T0 and
+    Pr = 0.71, split form with Pirozzoli's flux, LLF surface flux, BR1, the modal
+    indicator with FV-subcell blending, and the fourteen-stage RK scheme"""
+    mesh = box_mesh(K, 0.0, 2 * np.pi, N, amp=0.05 if curved else 0.0, seed=seed, rotate=rotate)
+    gamma, R = 1.4, 1.0
+    p0 = 1.0 / (gamma * Ma ** 2)
+    p = params(N, node_type=1, riemann=0, viscous=1, source=0, shock=1, gamma=gamma, R=R, Pr=0.71,
+               mu=1.0 / Re, alpha_max=alpha_max, volume_flux=1, viscosity=1, T_ref=p0 / R,
+               time_scheme=1)
+    X = mesh.points(lgl_points(N))
+    # the fourteen-stage scheme is stable at about 3.2 times the five-stage step
+    return Workload("ctgv", p, mesh, tgv_state(X, Ma, gamma, R=R), steps, cfl=2.5,
+                    extra=dict(Ma=Ma, Re=Re, p0=p0))
 
 
 def blast_workload(K=32, N=5, steps=200, seed=0, rotate=False):
