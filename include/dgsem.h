@@ -4,15 +4,19 @@
  * The library evaluates the discontinuous Galerkin spectral element time
  * derivative of the compressible Navier-Stokes equations on curved,
  * unstructured hexahedral meshes with periodic connectivity, and advances it
- * with the five-stage fourth-order low-storage Runge-Kutta scheme.
+ * with a low-storage Runge-Kutta scheme (five or fourteen stages).
  * Paper: Kurz, Kempf et al., GALAEXI (arXiv 2404.12703):
  *   equations           Sec. 2.1, Eqs. nse, eos_p, eos_T
  *   mapping, metrics    Sec. 2.2 "Mapping the Equations" (curl form)
  *   operator            Sec. 2.2 Eq. dgsem; Table tab:dg_routines; App. A
  *   BR1 lifting         Sec. 2.2 "Second-Order Equations", Eq. lifting
- *   time integration    Sec. 2.2 "Time integration" (Carpenter-Kennedy 4(5))
+ *   split form          Sec. 2.2 "Nonlinear Stability" (Pirozzoli's two-point flux)
+ *   viscosity law       Sec. 2.1 Eq. sutherland
+ *   time integration    Sec. 2.2 "Time integration" (Carpenter-Kennedy 4(5);
+ *                       Niegemann et al.'s fourteen stages)
  *   shock capturing     Sec. 2.3 (convex DG/FV-subcell blend, a-priori indicator)
- *   throughput metric   Sec. 4.2 (PID)
+ *   dissipation rates   Sec. 5.2 (solenoidal and dilatational, from the lifted gradients)
+ *   throughput metric   Sec. 4.2 (PID); memory per DOF Sec. 4.3
  *
  * Conventions shared by every entry point
  *   - All functions are extern "C"; no exception crosses the ABI.  They return
@@ -44,7 +48,7 @@
 extern "C" {
 #endif
 
-#define DG_ABI_VERSION 1
+#define DG_ABI_VERSION 2
 
 typedef int32_t dg_status;
 enum {
@@ -58,23 +62,42 @@ enum {
   DG_ESTATE = -7      /* object unusable after an earlier device error, or wrong call order */
 };
 
-/* Problem parameters.  gamma, R, Pr, mu: perfect gas with constant viscosity
- * and heat conductivity lambda = gamma R mu / ((gamma - 1) Pr) (Sec. 2.1). */
+/* Problem parameters.  gamma, R, Pr, mu: perfect gas; heat conductivity
+ * lambda = gamma R mu(T) / ((gamma - 1) Pr) (Sec. 2.1), mu constant or by
+ * Sutherland's law. */
 typedef struct dg_params {
   int32_t abi_version;     /* must be DG_ABI_VERSION                                   */
-  int32_t N;               /* polynomial degree, 1 <= N <= 9 (kernels built for 1..9)  */
-  int32_t nodes;           /* 0 Gauss-Legendre, 1 Gauss-Lobatto (required by shock capturing) */
+  int32_t N;               /* polynomial degree, 1 <= N <= 9 (see below for the cap)   */
+  int32_t nodes;           /* 0 Gauss-Legendre, 1 Gauss-Lobatto (required by shock capturing and the split form) */
   int32_t riemann;         /* 0 local Lax-Friedrichs, 1 Roe (no entropy fix)           */
   int32_t precision;       /* 0 FP64; 1 mixed: FP32 fluxes and contractions, FP64 state, RK, setup */
   int32_t viscous;         /* 0 Euler, 1 Navier-Stokes with BR1 lifting                */
   int32_t source;          /* 0 none, 1 manufactured-solution source of Sec. 5.1 (see below) */
   int32_t shock_capturing; /* 1: per-element DG/FV blend with the modal indicator (2 <= N <= 7) */
-  int32_t check_finite;    /* 1: dg_advance verifies the state is finite at its end   */
+  int32_t check_finite;    /* 1: dg_advance checks the state after every step and reports the first non-finite one */
   int32_t reserved;
-  double gamma, R, Pr, mu;
+  double gamma, R, Pr, mu; /* mu: the constant viscosity, or mu(T_ref) under Sutherland's law */
   double alpha_max, alpha_min; /* blending clip: alpha < alpha_min -> 0, > 1-alpha_min -> 1, then min(alpha, alpha_max) */
   double ind_a, ind_c, ind_s;  /* threshold T = ind_a 10^(-ind_c (N+1)^(1/4)); alpha = 1/(1+exp(-ind_s/T (E-T))) */
+  /* ---- since ABI version 2 ---- */
+  int32_t volume_flux;     /* 0 standard weak-form volume integral (Eq. dgsem);
+                              1 split form with Pirozzoli's kinetic-energy-preserving two-point flux
+                                (Sec. 2.2 "Nonlinear Stability"; Gauss-Lobatto nodes only) */
+  int32_t viscosity_law;   /* 0 constant mu; 1 Sutherland (Sec. 2.1 Eq. sutherland):
+                              mu(T) = mu 1.4042 (T/T_ref)^(3/2) / (T/T_ref + 0.4042) */
+  int32_t time_scheme;     /* 0 five-stage Carpenter-Kennedy 4(5); 1 fourteen-stage fourth-order
+                              scheme of Niegemann, Diehl and Busch (both 2N-storage, Sec. 2.2 "Time integration") */
+  int32_t alpha_smooth;    /* 0: alpha is the element's own indicator value, local to the element (Sec. 2.3);
+                              1: raised to half the largest face neighbour's value, then alpha < alpha_min -> 0
+                                 and min(alpha, alpha_max) (Hennemann's smoothing, not in the paper) */
+  double T_ref;            /* Sutherland reference temperature (> 0 when viscosity_law = 1) */
+  double p_ref;            /* mixed precision only: background pressure taken out of the FP32
+                              arithmetic (the energy is carried as rho e - p_ref/(gamma-1));
+                              0 = none.  Ignored in FP64. */
 } dg_params;
+/* The degree cap: one workgroup holds one element's (N+1)^3 tile and its face
+ * arrays in LDS (at N = 9 the FP64 volume sweep takes 138 KB of the 160 KB of
+ * a CU); N >= 10 would need a tile split across workgroups. */
 /* source = 1: rho = 2 + 0.1 sin(pi(x+y+z-t)), u = v = w = 1, p = rho is an exact
  * solution once 0.1 pi cos(pi(x+y+z-t)) (2, 3, 3, 3, 2(3 gamma-2)/(gamma-1)) is added. */
 
@@ -114,10 +137,16 @@ dg_status dg_create(const dg_params *p, const dg_mesh *m, void *d_workspace, siz
                     void *hip_stream, dg_solver **out);
 
 /* Load the state U ([5][E][(N+1)^3] doubles; host memory if on_device == 0,
- * else device memory) and set the time to t. */
+ * else device memory) and set the time to t: the initial condition of the
+ * semi-discrete system (Sec. 2.2, Eq. dgsem, integrated in time as in
+ * "Time integration").  The RK register restarts: the next step's first
+ * stage ignores what it held (A_1 = 0), so a state restored after a failure
+ * steps cleanly.  Host copies synchronise the stream. */
 dg_status dg_set_state(dg_solver *s, const double *U, int32_t on_device, double t);
 
-/* Copy the state out (host: synchronises the stream) and return the time. */
+/* Copy the state out (host: synchronises the stream) and return the time.
+ * Time stepping keeps every array on the device; the host reads the solution
+ * back for analysis only (Sec. 3, design principles). */
 dg_status dg_get_state(dg_solver *s, double *U, int32_t on_device, double *t);
 
 /* Stable time step of the current state: min over nodes of
@@ -126,11 +155,14 @@ dg_status dg_get_state(dg_solver *s, double *U, int32_t on_device, double *t);
  * The paper does not give a formula; this is an estimate from the 1-D spectra. */
 dg_status dg_stable_dt(dg_solver *s, double cfl, double dfl, double *dt);
 
-/* Advance n_steps steps of size dt with the five-stage low-storage RK scheme
- * (Sec. 2.2 "Time integration"); each stage evaluates the full operator:
- * ProlongToFace, BR1 lifting, FillFlux, VolInt, SurfInt, ApplyJac, optional
- * FV blending (Sec. 2.3), then du = A_s du + dt R; U = U + B_s du.
- * Asynchronous; with check_finite it synchronises once and may return DG_ENONFINITE. */
+/* Advance n_steps steps of size dt with the low-storage RK scheme of
+ * time_scheme (Sec. 2.2 "Time integration"); each stage evaluates the full
+ * operator: ProlongToFace, BR1 lifting, FillFlux, VolInt, SurfInt, ApplyJac,
+ * optional FV blending (Sec. 2.3), then du = A_s du + dt R; U = U + B_s du.
+ * Asynchronous.  With check_finite the state is checked on the device after
+ * every step and the call synchronises after each check: at the first
+ * non-finite step it stops, leaves that step's state and time in the solver,
+ * names the step in dg_last_error and returns DG_ENONFINITE. */
 dg_status dg_advance(dg_solver *s, int32_t n_steps, double dt);
 
 /* One evaluation of the time derivative R(U, t) (Eq. dgsem) into Ut
@@ -149,7 +181,17 @@ dg_status dg_set_alpha(dg_solver *s, const double *alpha_host);
  * rho0 = U0 = 1), out[6] = |Omega| = sum w J. */
 dg_status dg_integrals(dg_solver *s, double out[7]);
 
-/* Wait for all work the solver enqueued. */
+/* Dissipation rates of Sec. 5.2 of the current state, from the BR1-lifted
+ * gradients g of one volume sweep (state and RK register unchanged):
+ * out[0] = eps_S = (1/|Omega|) sum w J mu(T) |curl u|^2 (solenoidal),
+ * out[1] = eps_D = (4/(3|Omega|)) sum w J mu(T) (div u)^2 (dilatational),
+ * |Omega| = sum w J; with rho0 = U0 = L = 1 the paper's mu(T)/(mu0 Re) is
+ * mu(T).  Per-element partial sums are reduced in a fixed order on the host
+ * (synchronises).  DG_EINVAL without the viscous operator. */
+dg_status dg_dissipation(dg_solver *s, double out[2]);
+
+/* Wait for all work the solver enqueued on its stream (the host side of the
+ * asynchronous stage launches of Sec. 3.2). */
 dg_status dg_synchronize(dg_solver *s);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -187,8 +229,10 @@ typedef struct dg_timing {
 
 /* Create a server over a caller-owned device arena (d_arena, arena_bytes);
  * at most hbm_budget bytes of it are used at once and at most max_active
- * requests run together.  Work goes on hip_stream; uploads and downloads on
- * hip_copy_stream (may equal hip_stream). */
+ * requests run together.  Work goes on hip_stream; uploads on
+ * hip_copy_stream (may equal hip_stream).  The server allocates its pinned
+ * host memory here, once: descriptor mirrors and 16 staging slots of 16 MiB
+ * through which finished states are copied out in chunks. */
 dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget, int32_t max_active,
                            void *hip_stream, void *hip_copy_stream, dg_server **out);
 

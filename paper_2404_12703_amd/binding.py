@@ -19,7 +19,7 @@ DG_OK, DG_EINVAL, DG_EMESH, DG_ENOMEM, DG_EDEVICE, DG_ENONFINITE, DG_EBUSY, DG_E
 _NAMES = {-1: "DG_EINVAL", -2: "DG_EMESH", -3: "DG_ENOMEM", -4: "DG_EDEVICE", -5: "DG_ENONFINITE",
           -6: "DG_EBUSY", -7: "DG_ESTATE"}
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class DGError(RuntimeError):
@@ -34,7 +34,9 @@ class dg_params(C.Structure):
                 ("shock_capturing", C.c_int32), ("check_finite", C.c_int32), ("reserved", C.c_int32),
                 ("gamma", C.c_double), ("R", C.c_double), ("Pr", C.c_double), ("mu", C.c_double),
                 ("alpha_max", C.c_double), ("alpha_min", C.c_double), ("ind_a", C.c_double),
-                ("ind_c", C.c_double), ("ind_s", C.c_double)]
+                ("ind_c", C.c_double), ("ind_s", C.c_double),
+                ("volume_flux", C.c_int32), ("viscosity_law", C.c_int32), ("time_scheme", C.c_int32),
+                ("alpha_smooth", C.c_int32), ("T_ref", C.c_double), ("p_ref", C.c_double)]
 
 
 class dg_mesh(C.Structure):
@@ -75,6 +77,7 @@ def lib():
             "dg_set_alpha": (i32, [vp, vp]),
             "dg_integrals": (i32, [vp, vp]),
             "dg_synchronize": (i32, [vp]),
+            "dg_dissipation": (i32, [vp, vp]),
             "dg_destroy": (None, [vp]),
             "dg_profile_enable": (i32, [vp, i32]),
             "dg_profile_read": (i32, [vp, i32, vp, vp]),
@@ -107,7 +110,10 @@ def make_params(p: dict) -> dg_params:
                      gamma=float(p.get("gamma", 1.4)), R=float(p.get("R", 1.0)), Pr=float(p.get("Pr", 0.72)),
                      mu=float(p.get("mu", 0.0)), alpha_max=float(p.get("alpha_max", 1.0)),
                      alpha_min=float(p.get("alpha_min", 0.001)), ind_a=float(p.get("ind_a", 0.5)),
-                     ind_c=float(p.get("ind_c", 1.8)), ind_s=float(p.get("ind_s", np.log(9999.0))))
+                     ind_c=float(p.get("ind_c", 1.8)), ind_s=float(p.get("ind_s", np.log(9999.0))),
+                     volume_flux=int(p.get("volume_flux", 0)), viscosity_law=int(p.get("viscosity", 0)),
+                     time_scheme=int(p.get("time_scheme", 0)), alpha_smooth=int(p.get("alpha_smooth", 0)),
+                     T_ref=float(p.get("T_ref", 1.0)), p_ref=float(p.get("p_ref", 0.0)))
 
 
 class _MeshArrays:
@@ -231,6 +237,12 @@ class Solver:
 
     def synchronize(self):
         _check(lib().dg_synchronize(self._h))
+
+    def dissipation(self):
+        """(eps_S, eps_D) of the current state"""
+        out = np.zeros(2)
+        _check(lib().dg_dissipation(self._h, C.c_void_p(out.ctypes.data)))
+        return out
 
     def profile(self, on: bool):
         _check(lib().dg_profile_enable(self._h, 1 if on else 0))

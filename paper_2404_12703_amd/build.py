@@ -38,7 +38,9 @@ def _compile(src):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+    # one translation unit per polynomial degree: compile them side by side
+    workers = max(1, min(16, os.cpu_count() or 4))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         results = list(ex.map(_compile, sources()))
     objs = [o for o, _ in results]
     if verbose:

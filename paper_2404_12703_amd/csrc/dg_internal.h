@@ -17,12 +17,14 @@ constexpr int NV = 5;   // conservative variables
 constexpr int NLIFT = 4; // lifted primitives u, v, w, T
 constexpr int NG = 12;  // lifted gradient components: 3 directions x 4 variables
 constexpr int N_MAX = 9;
+constexpr int MAX_STAGES = 14;  // low-storage RK stages of the longest scheme
 
 // Device view of one solve: every pointer and scalar a kernel needs for one
 // RK stage.  `real` is the arithmetic type of the time derivative (double
 // for FP64, float for the mixed form); state and RK register stay double.
 template <typename real>
 struct View {
+  using value_type = real;
   int64_t E;        // elements
   double *U;        // [5][E][n3]
   double *dU;       // [5][E][n3]   low-storage RK register
@@ -38,18 +40,25 @@ struct View {
   const double *Xs; // [3][E][n3] node positions (manufactured source only)
   const real *basis; // operator block, see BasisOffsets
   real *alpha;      // [E] blending factors
-  real *alpha_raw;  // [E] indicator values before neighbour propagation
+  real *alpha_raw;  // [E] indicator values of the elements (before the optional smoothing)
   const real *alpha_in; // [E] frozen blending factors or null
   int *bcnt;        // shock capturing: [2] entries of blist, used by alternate surface sweeps
   int *blist;       // shock capturing: [E] workgroups with a blended element, this sweep
+  double *diag;     // [E][3] per-element sums of the volume sweep: w J mu |curl u|^2, w J mu (div u)^2, w J; or null
   char *base;       // batched launches, in the argument view: the arena that the
                     // descriptors' pointer fields are byte offsets into
-  real gamma, Rgas, rRgas, mu, lambda; // perfect gas (rRgas = 1/R), constant viscosity and conductivity
+  real gamma, Rgas, rRgas, mu, lambda; // perfect gas (rRgas = 1/R); mu, lambda at T_ref under Sutherland's law
+  real rTref;       // 1/T_ref (Sutherland)
+  real kappa;       // lambda/mu = gamma R/((gamma - 1) Pr)
+  real cpR;         // gamma R/(gamma - 1): specific total enthalpy H = cpR T + |u|^2/2
   double Pr;        // Prandtl number (time-step estimate only)
   double t, dt, rkA, rkB;       // stage time, step, LSERK coefficients
   int cur;          // trace buffer read this stage (0: Utr0, 1: Utr1)
   int bpar;         // entry of bcnt this surface sweep counts in; it clears the other
   int viscous, riemann, source, shock;
+  int split;        // split-form volume integral with Pirozzoli's two-point flux (Gauss-Lobatto)
+  int visc_law;     // 0 constant viscosity, 1 Sutherland's law
+  int alpha_smooth; // 1: raise alpha to half the largest face neighbour's indicator value
   int lgl;          // Gauss-Lobatto nodes: l(-1), l(+1) are unit vectors, l-hat vanishes off the end nodes
   int remap;        // XCD-contiguous block order (single solve)
   real ind_a, ind_c, ind_s, alpha_min, alpha_max, ind_T; // indicator (ind_T precomputed threshold)
@@ -112,7 +121,28 @@ __host__ __device__ inline void orient_map(int code, int p, int q, int N, int &p
 // blk_start[r] is the first block of request r (prefix sums, nreq+1 entries,
 // device).  A single solve passes nreq = 0 and its view in v0.
 // ---------------------------------------------------------------------------
-enum Kernel { K_TRACE = 0, K_LIFT = 1, K_RHS = 2, K_COUNT = 3 };
+// K_DIAG: the volume sweep with the per-element dissipation sums (View::diag)
+enum Kernel { K_TRACE = 0, K_LIFT = 1, K_RHS = 2, K_DIAG = 3 };
+
+// workgroup shape of an element block at degree N
+template <int N>
+struct Sz {
+  static constexpr int n = N + 1, n2 = n * n, n3 = n2 * n, nf = 6 * n2;
+  static constexpr int epb = (256 / n3) > 1 ? 256 / n3 : 1;  // elements per workgroup
+  static constexpr int threads = ((epb * n3 + 63) / 64) * 64;
+  // waves per SIMD to plan registers for (128 VGPRs): two 512-thread or four
+  // 256-thread workgroups per CU
+  static constexpr int minw = (threads == 512 || threads == 256) ? 4 : 1;
+};
+
+// the kernels of one degree (kernels_n<N>.hip); the dispatch over N is launch()
+template <int N, typename real>
+hipError_t launch_n(Kernel k, int mode, const View<real> *views, const int *blk_start, int nreq, int blocks,
+                    const View<real> &v0, hipStream_t st);
+
+// the low-storage RK scheme of dg_params::time_scheme: stage count and
+// pointers to its A, B, c coefficients
+int rk_scheme(int scheme, const double **A, const double **B, const double **C);
 
 int blocks_per_elements(int N, int64_t E);  // number of blocks covering E elements
 int block_threads(int N);
@@ -126,7 +156,9 @@ template <typename real>
 hipError_t launch_dt(int N, const View<real> &v, double *scratch, int nblk, hipStream_t st);
 template <typename real>
 hipError_t launch_integrals(int N, const View<real> &v, double *scratch, int nblk, hipStream_t st);
+// sets *flag to 1 if U[0..count) holds a NaN or Inf (leaves it otherwise)
 hipError_t launch_finite(const double *U, int64_t count, int *flag, hipStream_t st);
+hipError_t launch_zero_int(int *p, int count, hipStream_t st);
 hipError_t launch_cast(const double *src, float *dst, int64_t count, hipStream_t st);
 
 }  // namespace dg

@@ -1,0 +1,9 @@
+// kernels_n3.hip -- the DGSEM kernels at polynomial degree 3 (templates in kernels.h).
+#include "kernels.h"
+
+namespace dg {
+template hipError_t launch_n<3, double>(Kernel, int, const View<double> *, const int *, int, int,
+                                        const View<double> &, hipStream_t);
+template hipError_t launch_n<3, float>(Kernel, int, const View<float> *, const int *, int, int,
+                                       const View<float> &, hipStream_t);
+}  // namespace dg

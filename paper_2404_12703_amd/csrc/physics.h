@@ -55,6 +55,34 @@ __device__ __forceinline__ void flux_visc(const real *P, const real *g, real mu,
   F[4] = tau[0] * P[1] + tau[1] * P[2] + tau[2] * P[3] + lambda * g[d * 4 + 3];
 }
 
+// Sec. 2.1 Eq. sutherland: the viscosity at temperature T, normalised by the
+// reference temperature: mu(T) = mu_ref 1.4042 th^(3/2) / (th + 0.4042), th = T/T_ref
+template <typename real>
+__device__ __forceinline__ real sutherland(real T, real mu_ref, real rTref) {
+  const real th = T * rTref;
+  return mu_ref * real(1.4042) * th * sqrt(th) / (th + real(0.4042));
+}
+
+// Sec. 2.2 "Nonlinear Stability": Pirozzoli's kinetic-energy-preserving
+// two-point flux of the split form along the unnormalised direction m (the
+// mean of the two nodes' metric vectors).  Arithmetic means of density,
+// velocity, pressure and specific total enthalpy; the mass flux carries
+// momentum and enthalpy.  Consistent (F#(U, U) = F(U).m) and symmetric.
+template <typename real>
+__device__ __forceinline__ void two_point_kep(real rL, real uL, real vL, real wL, real pL, real HL, real rR, real uR,
+                                              real vR, real wR, real pR, real HR, real m0, real m1, real m2,
+                                              real *F) {
+  const real rho = real(0.5) * (rL + rR);
+  const real u = real(0.5) * (uL + uR), v = real(0.5) * (vL + vR), w = real(0.5) * (wL + wR);
+  const real p = real(0.5) * (pL + pR), H = real(0.5) * (HL + HR);
+  const real mf = rho * (u * m0 + v * m1 + w * m2);
+  F[0] = mf;
+  F[1] = mf * u + p * m0;
+  F[2] = mf * v + p * m1;
+  F[3] = mf * w + p * m2;
+  F[4] = mf * H;
+}
+
 template <typename real>
 __device__ __forceinline__ void flux_normal(const real *U, const real *P, const real *nv, real *F) {
   real f[5];

@@ -74,12 +74,23 @@ struct Request {
   std::atomic<int> prep{PREP_WAITING};
   std::string prep_err;
   hipEvent_t ready = nullptr;  // set-up copies done
-  // retirement
+  // retirement: the state leaves through the server's pinned staging slots
   std::vector<double> result;
-  double *pinned = nullptr;
-  int *flag_host = nullptr;
-  hipEvent_t done_ev = nullptr;
-  bool retiring = false;
+  bool retiring = false, bad = false;
+  size_t issued = 0, copied = 0;  // bytes of the state sent to / landed in result
+};
+
+// Pinned host staging for retirement, allocated once at server creation:
+// finished states are copied out in chunks through these slots, so the
+// serving loop never allocates or frees pinned memory.
+constexpr size_t kStageChunk = size_t(16) << 20;
+constexpr int kStageSlots = 16;
+struct StageSlot {
+  char *host = nullptr;  // kStageChunk bytes + one int for the finiteness flag
+  hipEvent_t ev = nullptr;
+  int64_t req = 0;
+  size_t off = 0, bytes = 0;
+  bool busy = false, flag = false;
 };
 
 // Set-ups of meshes seen before, kept by the preparation thread (the only
@@ -216,7 +227,8 @@ struct dg_server {
   int desc_next = 0;
   hipStream_t gst[kGroupStreams] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kGroupStreams] = {};
-  int *flags_dev = nullptr;
+  StageSlot slots[kStageSlots];
+  std::vector<hipEvent_t> ev_free;  // events of admitted requests, reused
   // reqs and queue are shared with the preparation thread: changed under prep_mu
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::deque<int64_t> queue;
@@ -337,7 +349,14 @@ dg_status admit(dg_server *sv) {
     hipError_t e = setup_device(r.p, *r.host, base, r.L, sv->cst);
     if (e == hipSuccess)
       e = hipMemcpyAsync((char *)base + r.L.U, r.U0.data(), r.U0.size() * 8, hipMemcpyHostToDevice, sv->cst);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+    if (e == hipSuccess) {
+      if (!sv->ev_free.empty()) {
+        r.ready = sv->ev_free.back();
+        sv->ev_free.pop_back();
+      } else {
+        e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+      }
+    }
     if (e == hipSuccess) e = hipEventRecord(r.ready, sv->cst);
     if (e == hipSuccess) e = hipStreamWaitEvent(sv->st, r.ready, 0);
     if (e != hipSuccess) return server_fail(sv, e, "admission upload");
@@ -406,10 +425,12 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
   for (size_t r = 0; r < grp.size(); ++r) {
     Request &q = *grp[r];
     View<real> v = view_of<real>(q);
-    v.t = q.t + RK_C[q.stage] * q.dt;
+    const double *A, *B, *C;
+    rk_scheme(q.p.time_scheme, &A, &B, &C);
+    v.t = q.t + C[q.stage] * q.dt;
     v.dt = q.dt;
-    v.rkA = RK_A[q.stage];
-    v.rkB = RK_B[q.stage];
+    v.rkA = A[q.stage];
+    v.rkB = B[q.stage];
     v.cur = q.cur;
     v.bpar = q.bpar;
     v.R = nullptr;
@@ -433,12 +454,13 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
 
 // one RK stage for every active request
 dg_status tick(dg_server *sv) {
-  // one group per kernel set: degree, precision, shock capturing, viscosity, nodes
+  // one group per kernel set: degree, precision, shock capturing, viscosity,
+  // volume form and nodes
   std::map<std::tuple<int, int, int, int, int>, std::vector<Request *>> groups;
   for (int64_t id : sv->active) {
     Request &r = *sv->reqs[id];
     if (r.retiring || r.step >= r.n_steps) continue;
-    groups[{r.p.N, r.p.precision, r.p.shock_capturing, r.p.viscous, r.p.nodes}].push_back(&r);
+    groups[{r.p.N, r.p.precision, r.p.shock_capturing, r.p.viscous, 2 * r.p.volume_flux + r.p.nodes}].push_back(&r);
   }
   if (groups.empty()) return DG_OK;
   hipError_t e = hipEventRecord(sv->fork_ev, sv->st);
@@ -453,7 +475,7 @@ dg_status tick(dg_server *sv) {
     std::vector<Request *> fresh, visc;
     for (Request *r : kv.second) {
       if (!r->traces_valid) fresh.push_back(r);
-      if (r->p.viscous || r->p.shock_capturing) visc.push_back(r);
+      if (r->p.viscous || r->p.shock_capturing || r->p.volume_flux) visc.push_back(r);
     }
     dg_status rc;
     rc = mixed ? launch_group<float>(sv, K_TRACE, N, fresh, gs) : launch_group<double>(sv, K_TRACE, N, fresh, gs);
@@ -466,7 +488,8 @@ dg_status tick(dg_server *sv) {
       r->traces_valid = true;
       r->cur ^= 1;
       r->bpar ^= 1;
-      if (++r->stage == 5) {
+      const double *A, *B, *C;
+      if (++r->stage == rk_scheme(r->p.time_scheme, &A, &B, &C)) {
         r->stage = 0;
         ++r->step;
         r->t = r->step * r->dt;
@@ -482,48 +505,62 @@ dg_status tick(dg_server *sv) {
   return DG_OK;
 }
 
-// start the copy-out of finished requests; release those whose copy is done
+// Copy finished requests out through the staging slots; release a request's
+// memory once its whole state has landed on the host.
 dg_status retire(dg_server *sv) {
+  // staging copies that have completed: into the requests' results
+  for (StageSlot &sl : sv->slots) {
+    if (!sl.busy) continue;
+    hipError_t q = hipEventQuery(sl.ev);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return server_fail(sv, q, "retirement copy");
+    Request &r = *sv->reqs[sl.req];
+    std::memcpy((char *)r.result.data() + sl.off, sl.host, sl.bytes);
+    if (sl.flag) r.bad = *(const int *)(sl.host + kStageChunk) != 0;
+    r.copied += sl.bytes;
+    sl.busy = false;
+  }
   std::vector<int64_t> keep;
   for (int64_t id : sv->active) {
     Request &r = *sv->reqs[id];
+    const size_t total = (size_t)5 * r.E * (r.p.N + 1) * (r.p.N + 1) * (r.p.N + 1) * 8;
+    int *flag = (int *)(sv->arena + r.off + r.L.scratch);
+    const double *U = (const double *)(sv->arena + r.off + r.L.U);
     if (!r.retiring && r.step >= r.n_steps) {
-      const size_t cnt = (size_t)5 * r.E * (r.p.N + 1) * (r.p.N + 1) * (r.p.N + 1);
-      hipError_t e = hipHostMalloc((void **)&r.pinned, cnt * 8, hipHostMallocDefault);
-      if (e == hipSuccess) e = hipHostMalloc((void **)&r.flag_host, 256 * sizeof(int), hipHostMallocDefault);
-      if (e != hipSuccess) return server_fail(sv, e, "pinned staging");
-      const double *U = (const double *)(sv->arena + r.off + r.L.U);
-      int *flags = (int *)(sv->arena + r.off + r.L.scratch);
-      e = launch_finite(U, (int64_t)cnt, flags, sv->st);
-      if (e == hipSuccess) e = hipMemcpyAsync(r.pinned, U, cnt * 8, hipMemcpyDeviceToHost, sv->st);
-      if (e == hipSuccess) e = hipMemcpyAsync(r.flag_host, flags, 256 * sizeof(int), hipMemcpyDeviceToHost, sv->st);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventRecord(r.done_ev, sv->st);
-      if (e != hipSuccess) return server_fail(sv, e, "retirement copy");
+      // the finiteness check runs after the last stage, before the copies
+      hipError_t e = launch_zero_int(flag, 1, sv->st);
+      if (e == hipSuccess) e = launch_finite(U, (int64_t)(total / 8), flag, sv->st);
+      if (e != hipSuccess) return server_fail(sv, e, "retirement check");
+      r.result.resize(total / 8);
       r.retiring = true;
+      r.issued = r.copied = 0;
+      r.bad = false;
     }
     if (r.retiring) {
-      hipError_t q = hipEventQuery(r.done_ev);
-      if (q == hipErrorNotReady) {
+      for (StageSlot &sl : sv->slots) {
+        if (r.issued >= total) break;
+        if (sl.busy) continue;
+        sl.req = id;
+        sl.off = r.issued;
+        sl.bytes = std::min(kStageChunk, total - r.issued);
+        sl.flag = r.issued + sl.bytes == total;
+        hipError_t e = hipMemcpyAsync(sl.host, (const char *)U + sl.off, sl.bytes, hipMemcpyDeviceToHost, sv->st);
+        if (e == hipSuccess && sl.flag)
+          e = hipMemcpyAsync(sl.host + kStageChunk, flag, sizeof(int), hipMemcpyDeviceToHost, sv->st);
+        if (e == hipSuccess) e = hipEventRecord(sl.ev, sv->st);
+        if (e != hipSuccess) return server_fail(sv, e, "retirement copy");
+        sl.busy = true;
+        r.issued += sl.bytes;
+      }
+      if (r.copied < total) {
         keep.push_back(id);
         continue;
       }
-      if (q != hipSuccess) return server_fail(sv, q, "retirement event");
-      const size_t cnt = (size_t)5 * r.E * (r.p.N + 1) * (r.p.N + 1) * (r.p.N + 1);
-      r.result.assign(r.pinned, r.pinned + cnt);
-      bool bad = false;
-      for (int b = 0; b < 256; ++b) bad |= r.flag_host[b] != 0;
-      (void)hipHostFree(r.pinned);
-      (void)hipHostFree(r.flag_host);
-      r.pinned = nullptr;
-      r.flag_host = nullptr;
-      (void)hipEventDestroy(r.done_ev);
-      r.done_ev = nullptr;
-      if (r.ready) (void)hipEventDestroy(r.ready);
+      if (r.ready) sv->ev_free.push_back(r.ready);
       r.ready = nullptr;
       r.host.reset();
       sv->alloc.release(r.off, r.bytes);
-      r.state = bad ? DG_REQ_FAILED : DG_REQ_DONE;
+      r.state = r.bad ? DG_REQ_FAILED : DG_REQ_DONE;
       r.t_done = sv->now();
       continue;
     }
@@ -565,6 +602,21 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
     if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[s], sv->st);
     if (e != hipSuccess) return fail(DG_EDEVICE, std::string("server set-up: ") + hipGetErrorString(e));
   }
+  for (StageSlot &sl : sv->slots) {
+    hipError_t e = hipHostMalloc((void **)&sl.host, kStageChunk + 256, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (StageSlot &t : sv->slots) {
+        if (t.host) (void)hipHostFree(t.host);
+        if (t.ev) (void)hipEventDestroy(t.ev);
+      }
+      for (int q = 0; q < kDescSlots; ++q) {
+        if (sv->desc_host[q]) (void)hipHostFree(sv->desc_host[q]);
+        if (sv->desc_ev[q]) (void)hipEventDestroy(sv->desc_ev[q]);
+      }
+      return fail(DG_EDEVICE, std::string("server staging: ") + hipGetErrorString(e));
+    }
+  }
   {
     hipError_t e = hipEventCreateWithFlags(&sv->fork_ev, hipEventDisableTiming);
     for (int i = 0; i < kGroupStreams && e == hipSuccess; ++i) {
@@ -580,6 +632,10 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
       for (int s = 0; s < kDescSlots; ++s) {
         if (sv->desc_host[s]) (void)hipHostFree(sv->desc_host[s]);
         if (sv->desc_ev[s]) (void)hipEventDestroy(sv->desc_ev[s]);
+      }
+      for (StageSlot &t : sv->slots) {
+        (void)hipHostFree(t.host);
+        (void)hipEventDestroy(t.ev);
       }
       return fail(DG_EDEVICE, std::string("server streams: ") + hipGetErrorString(e));
     }
@@ -693,10 +749,12 @@ void dg_server_destroy(dg_server *sv) {
   if (sv->cst != sv->st) (void)hipStreamSynchronize(sv->cst);
   for (auto &kv : sv->reqs) {
     Request &r = *kv.second;
-    if (r.pinned) (void)hipHostFree(r.pinned);
-    if (r.flag_host) (void)hipHostFree(r.flag_host);
-    if (r.done_ev) (void)hipEventDestroy(r.done_ev);
     if (r.ready) (void)hipEventDestroy(r.ready);
+  }
+  for (hipEvent_t ev : sv->ev_free) (void)hipEventDestroy(ev);
+  for (StageSlot &sl : sv->slots) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
   for (int i = 0; i < kGroupStreams; ++i) {
     if (sv->gst[i]) {

@@ -3,9 +3,11 @@
 // derivative runs in the HIP kernels of kernels.hip.
 //
 // Paper (GALAEXI, arXiv 2404.12703): the time-stepping loop of Sec. 2.2
-// ("Time integration": Carpenter-Kennedy five-stage fourth-order 2N-storage
-// scheme) around the DG operator of Eq. dgsem; all of it on the device with
-// no host transfers during time stepping (Sec. 3, design principles).
+// ("Time integration": Carpenter-Kennedy five-stage or Niegemann et al.
+// fourteen-stage fourth-order 2N-storage schemes) around the DG operator of
+// Eq. dgsem; all of it on the device with no host transfers during time
+// stepping (Sec. 3, design principles).  The dissipation rates of Sec. 5.2
+// come from one volume sweep with per-element sums switched on.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +18,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "dg_internal.h"
@@ -39,6 +42,36 @@ const double RK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 136
 const double RK_C[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
                         2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
+// Niegemann, Diehl and Busch (2012): fourteen-stage fourth-order 2N-storage
+// scheme with a stability region stretched along the imaginary axis (the
+// scheme of the paper's application runs); published coefficients
+const double RK14_A[14] = {0.0, -0.7188012108672410, -0.7785331173421570, -0.0053282796654044,
+                           -0.8552979934029281, -3.9564138245774565, -1.5780575380587385,
+                           -2.0837094552574054, -0.7483334182761610, -0.7032861106563359,
+                           0.0013917096117681, -0.0932075369637460, -0.9514200470875948,
+                           -7.1151571693922548};
+const double RK14_B[14] = {0.0367762454319673, 0.3136296607553959, 0.1531848691869027, 0.0030097086818182,
+                           0.3326293790646110, 0.2440251405350864, 0.3718879239592277, 0.6204126221582444,
+                           0.1524043173028741, 0.0760894927419266, 0.0077604214040978, 0.0024647284755382,
+                           0.0780348340049386, 5.5059777270269628};
+const double RK14_C[14] = {0.0, 0.0367762454319673, 0.1249685262725025, 0.2446177702277698,
+                           0.2476149531070420, 0.2969311120382472, 0.3978149645802642, 0.5270854589440328,
+                           0.6981269994175695, 0.8190890835352128, 0.8527059887098624, 0.8604711817462826,
+                           0.8627060376969976, 0.8734213127600976};
+
+int rk_scheme(int scheme, const double **A, const double **B, const double **C) {
+  if (scheme == 1) {
+    *A = RK14_A;
+    *B = RK14_B;
+    *C = RK14_C;
+    return 14;
+  }
+  *A = RK_A;
+  *B = RK_B;
+  *C = RK_C;
+  return 5;
+}
+
 dg_status check_params(const dg_params *p) {
   if (!p) return fail(DG_EINVAL, "params is NULL");
   if (p->abi_version != DG_ABI_VERSION) return fail(DG_EINVAL, "abi_version mismatch");
@@ -52,6 +85,14 @@ dg_status check_params(const dg_params *p) {
     return fail(DG_EINVAL, "need gamma > 1, R > 0, Pr > 0, mu >= 0");
   if (p->shock_capturing && !(p->alpha_max >= 0.0 && p->alpha_max <= 1.0 && p->alpha_min >= 0.0 && p->ind_a > 0.0))
     return fail(DG_EINVAL, "bad indicator parameters");
+  if (p->volume_flux != 0 && p->volume_flux != 1) return fail(DG_EINVAL, "volume_flux must be 0 or 1");
+  if (p->volume_flux == 1 && p->nodes != 1) return fail(DG_EINVAL, "the split form needs Gauss-Lobatto nodes");
+  if (p->viscosity_law != 0 && p->viscosity_law != 1) return fail(DG_EINVAL, "viscosity_law must be 0 or 1");
+  if (p->viscosity_law == 1 && !(p->T_ref > 0.0 && p->mu > 0.0))
+    return fail(DG_EINVAL, "Sutherland's law needs T_ref > 0 and mu > 0");
+  if (p->time_scheme != 0 && p->time_scheme != 1) return fail(DG_EINVAL, "time_scheme must be 0 or 1");
+  if (p->alpha_smooth != 0 && p->alpha_smooth != 1) return fail(DG_EINVAL, "alpha_smooth must be 0 or 1");
+  if (!std::isfinite(p->p_ref) || p->p_ref < 0.0) return fail(DG_EINVAL, "p_ref must be finite and >= 0");
   return DG_OK;
 }
 
@@ -80,7 +121,9 @@ Layout make_layout(const dg_params &p, int64_t E) {
   // the two sweeps exchange each side's viscous face flux (4 values per face
   // node, viscous only) and the volume integral (5 per node)
   L.Hv = p.viscous ? take(4 * E * 6 * n2 * rs) : SIZE_MAX;
-  L.Vol = (p.viscous || p.shock_capturing) ? take(5 * E * n3 * rs) : SIZE_MAX;
+  L.Vol = (p.viscous || p.shock_capturing || p.volume_flux) ? take(5 * E * n3 * rs) : SIZE_MAX;
+  // per-element dissipation sums of dg_dissipation (viscous only)
+  L.diag = p.viscous ? take(3 * E * sizeof(double)) : SIZE_MAX;
   L.conn = take(6 * E * sizeof(int2));
   L.Xs = p.source ? take(3 * E * n3 * 8) : SIZE_MAX;
   L.basis = take(BasisOffsets(n).total * rs);
@@ -118,6 +161,7 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.alpha_in = nullptr;
   v.bcnt = (int *)at(L.blend);
   v.blist = v.bcnt ? v.bcnt + 2 : nullptr;
+  v.diag = nullptr;  // [E][3] sums, set for one sweep by dg_dissipation
   v.base = nullptr;
   v.gamma = (real)p.gamma;
   v.Rgas = (real)p.R;
@@ -125,6 +169,12 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.mu = (real)p.mu;
   v.lambda = (real)(p.gamma * p.R * p.mu / ((p.gamma - 1.0) * p.Pr));
   v.Pr = p.Pr;
+  v.rTref = (real)(p.viscosity_law ? 1.0 / p.T_ref : 1.0);
+  v.kappa = (real)(p.gamma * p.R / ((p.gamma - 1.0) * p.Pr));
+  v.cpR = (real)(p.gamma * p.R / (p.gamma - 1.0));
+  v.split = p.volume_flux;
+  v.visc_law = p.viscosity_law;
+  v.alpha_smooth = p.alpha_smooth;
   v.t = 0.0;
   v.dt = 0.0;
   v.rkA = 0.0;
@@ -291,7 +341,7 @@ static hipError_t stage(dg_solver *s, int mode, double t, double dt, double A, d
     if (e != hipSuccess) return e;
     s->traces_valid = true;
   }
-  if (s->p.viscous || s->p.shock_capturing) {  // lifting and/or the indicator
+  if (s->p.viscous || s->p.shock_capturing || s->p.volume_flux) {  // lifting, indicator, split form
     e = run_kernel<real>(s, K_LIFT, 0, v);
     if (e != hipSuccess) return e;
   }
@@ -304,10 +354,12 @@ static hipError_t stage(dg_solver *s, int mode, double t, double dt, double A, d
 
 template <typename real>
 static hipError_t advance_impl(dg_solver *s, int nsteps, double dt) {
+  const double *A, *B, *C;
+  const int ns = rk_scheme(s->p.time_scheme, &A, &B, &C);
   for (int st = 0; st < nsteps; ++st) {
     const double t0 = s->t;
-    for (int k = 0; k < 5; ++k) {
-      hipError_t e = stage<real>(s, 0, t0 + RK_C[k] * dt, dt, RK_A[k], RK_B[k], nullptr);
+    for (int k = 0; k < ns; ++k) {
+      hipError_t e = stage<real>(s, 0, t0 + C[k] * dt, dt, A[k], B[k], nullptr);
       if (e != hipSuccess) return e;
     }
     s->t = t0 + dt;
@@ -423,18 +475,25 @@ dg_status dg_get_state(dg_solver *s, double *U, int32_t on_device, double *t) {
 dg_status dg_advance(dg_solver *s, int32_t n_steps, double dt) {
   CHECK_SOLVER(s);
   if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "need n_steps >= 0 and dt > 0");
-  hipError_t e = solver_advance(s, n_steps, dt);
-  if (e != hipSuccess) return device_error(s, e, "dg_advance");
-  if (s->p.check_finite) {
-    int *flags = (int *)((char *)s->ws + s->L.scratch);
-    size_t count = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1);
-    e = launch_finite((const double *)((char *)s->ws + s->L.U), count, flags, s->st);
-    std::vector<int> h(256);
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), flags, 256 * sizeof(int), hipMemcpyDeviceToHost, s->st);
+  if (!s->p.check_finite) {
+    hipError_t e = solver_advance(s, n_steps, dt);
+    if (e != hipSuccess) return device_error(s, e, "dg_advance");
+    return DG_OK;
+  }
+  // checked stepping: one step, a finiteness flag on the device, its read-back
+  int *flag = (int *)((char *)s->ws + s->L.scratch);
+  const size_t count = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1);
+  for (int st = 0; st < n_steps; ++st) {
+    hipError_t e = solver_advance(s, 1, dt);
+    if (e == hipSuccess) e = launch_zero_int(flag, 1, s->st);
+    if (e == hipSuccess) e = launch_finite((const double *)((char *)s->ws + s->L.U), (int64_t)count, flag, s->st);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return device_error(s, e, "dg_advance finiteness check");
-    for (int x : h)
-      if (x) return fail(DG_ENONFINITE, "state is not finite after dg_advance");
+    if (h)
+      return fail(DG_ENONFINITE, "state not finite after step " + std::to_string(st + 1) + " of " +
+                                     std::to_string(n_steps) + " (t = " + std::to_string(s->t) + ")");
   }
   return DG_OK;
 }
@@ -491,6 +550,46 @@ dg_status dg_integrals(dg_solver *s, double out[7]) {
   for (int c = 0; c < 5; ++c) out[c] = acc[c];
   out[5] = acc[5] / acc[6];
   out[6] = acc[6];
+  return DG_OK;
+}
+
+dg_status dg_dissipation(dg_solver *s, double out[2]) {
+  CHECK_SOLVER(s);
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  if (!s->p.viscous) return fail(DG_EINVAL, "the dissipation rates need the viscous operator");
+  // one volume sweep of the current state with the per-element sums on; it
+  // writes only the stage temporaries (volume integral, viscous face fluxes)
+  double *d = (double *)((char *)s->ws + s->L.diag);
+  hipError_t e = hipSuccess;
+  auto sweep = [&](auto &v) {
+    using real = typename std::remove_reference<decltype(v)>::type::value_type;
+    v.t = s->t;
+    v.cur = s->cur;
+    v.bpar = s->bpar;
+    v.R = nullptr;
+    if (!s->traces_valid) {
+      e = run_kernel<real>(s, K_TRACE, 0, v);
+      if (e != hipSuccess) return;
+      s->traces_valid = true;
+    }
+    v.diag = d;
+    e = run_kernel<real>(s, K_DIAG, 0, v);
+    v.diag = nullptr;
+  };
+  if (s->mixed) sweep(s->vf);
+  else sweep(s->vd);
+  std::vector<double> h(3 * (size_t)s->E);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return device_error(s, e, "dg_dissipation");
+  double sS = 0.0, sD = 0.0, vol = 0.0;
+  for (int64_t el = 0; el < s->E; ++el) {
+    sS += h[3 * el];
+    sD += h[3 * el + 1];
+    vol += h[3 * el + 2];
+  }
+  out[0] = sS / vol;
+  out[1] = 4.0 / 3.0 * sD / vol;
   return DG_OK;
 }
 

@@ -14,7 +14,8 @@ constexpr int kRedBlocks = 1024;  // blocks of the reduction kernels
 
 // byte offsets of every array inside the caller's workspace (SIZE_MAX: absent)
 struct Layout {
-  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Hv, Vol, conn, Xs, basis, alpha, alpha_raw, alpha_in, blend, scratch, total;
+  size_t U, dU, Ja, invJ, NS, Utr0, Utr1, Hv, Vol, diag, conn, Xs, basis, alpha, alpha_raw, alpha_in, blend, scratch,
+      total;
 };
 
 Layout make_layout(const dg_params &p, int64_t E);

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported():
     assert len(names) >= 20
     for nm in names:
         assert hasattr(raw, nm), nm
-    assert b.lib().dg_abi_version() == 1
+    assert b.lib().dg_abi_version() == 2
 
 
 def test_workspace_bytes_and_parameter_checks():

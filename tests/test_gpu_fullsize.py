@@ -1,0 +1,79 @@
+"""GPU parity at the benchmark workloads' full sizes, over many steps: the
+curved Taylor-Green vortex (24^3 elements, N = 7, 7.1M DOF) after 100 steps
+against the oracle to 1e-10, and the shock-capturing blast (32^3 elements,
+N = 5 Lobatto, 7.1M DOF) over 20 steps with the blending factors of both
+sides compared at the end.  The oracle runs on every host core in chunks of
+steps, printing each chunk (a few minutes in all)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_steps(o, U, dt, n, chunk, label):
+    t0 = time.time()
+    for c in range(0, n, chunk):
+        k = min(chunk, n - c)
+        U = o.advance(U, dt, k, t0=c * dt)
+        _say(f"  [{label}] oracle steps {c + k}/{n} ({time.time() - t0:.0f} s)")
+    return U
+
+
+def test_tgv_24cubed_hundred_steps():
+    import paper_2404_12703_amd as P
+    wl = W.tgv_workload(K=24, N=7, steps=100)
+    _say("[tgv 24^3 N=7, 100 steps]")
+    o = O.Oracle(wl.params, wl.mesh)
+    dt = o.stable_dt(wl.U0)
+    s = P.Solver(wl.params, wl.mesh)
+    s.set_state(wl.U0, 0.0)
+    s.advance(100, dt)
+    Ug = s.state()
+    Ig = s.integrals()
+    del s
+    Uo = _oracle_steps(o, wl.U0, dt, 100, 10, "tgv")
+    e, ed = rel(Ug, Uo), rel(Ug - wl.U0, Uo - wl.U0)
+    Io = o.integrals(Uo)
+    _say(f"  state rel L2 {e:.3e}, change over 100 steps {ed:.3e}, E_k {Ig[5]:.12e} vs {Io[5]:.12e}")
+    assert e <= 1e-10
+    assert ed <= 1e-9
+    assert abs(Ig[5] - Io[5]) <= 1e-12 * abs(Io[5])
+
+
+def test_blast_32cubed_twenty_steps():
+    import paper_2404_12703_amd as P
+    wl = W.blast_workload(K=32, N=5, steps=20)
+    _say("[blast 32^3 N=5, 20 steps]")
+    o = O.Oracle(wl.params, wl.mesh)
+    dt = o.stable_dt(wl.U0, wl.cfl, wl.cfl)
+    s = P.Solver(wl.params, wl.mesh)
+    s.set_state(wl.U0, 0.0)
+    s.advance(20, dt)
+    Ug = s.state()
+    ag = s.alpha()
+    del s
+    Uo = _oracle_steps(o, wl.U0, dt, 20, 5, "blast")
+    ao = o.alpha()
+    flips = int(np.sum((ag > 0) != (ao > 0)))
+    e, ed = rel(Ug, Uo), rel(Ug - wl.U0, Uo - wl.U0)
+    _say(f"  blended {np.mean(ao > 0):.4f}, flips {flips}, max |dalpha| {np.abs(ag - ao).max():.2e}, "
+         f"state {e:.3e}, change {ed:.3e}")
+    assert flips == 0
+    assert np.abs(ag - ao).max() <= 1e-10
+    assert e <= 1e-11
+    assert ed <= 1e-9

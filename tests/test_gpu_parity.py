@@ -1,7 +1,9 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
 the same seeded inputs.  Tolerances: relative L2 over all variables and nodes,
-stacked; 1e-12 after one step and 1e-10 after 100 steps for the state, and
-for single evaluations of the time derivative the bound each case states."""
+stacked; 1e-12 after one step and 1e-10 after 100 steps for the state; for
+single evaluations of the time derivative 1e-12, or for the Taylor-Green
+workloads with their large background pressure the bound tgv_rhs_bound(K)
+derives."""
 import sys
 
 import numpy as np
@@ -71,15 +73,21 @@ CASES = ["mms_k4_n3", "tgv_curved_rot_k3_n7", "tgv_curved_k2_n5_llf", "ragged_n3
          "euler_n2_rot", "n1_lgl", "lgl_n5_curved", "n9_single"]
 
 
+def tgv_rhs_bound(K):
+    """One-evaluation parity bound for the Taylor-Green workloads at Ma = 0.1.
+    Their pressure carries the background p0 = 71.4 while |grad p| ~ 0.06: every
+    pressure flux is rounded at eps p0, and the differentiation that cancels
+    the background amplifies that by (N+1)^2 K / L against |R|.  Each side
+    (oracle, GPU) carries this round-off independently, so their difference
+    grows linearly with K: measured 1.17e-11 at K = 3 and 1.01e-10 at K = 24
+    (N = 7), 3.9e-12 K to 4.2e-12 K.  The bound is 6e-12 K; where the
+    background is O(1) the bound is 1e-12."""
+    return 6e-12 * K
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_rhs_parity(name):
-    """one evaluation of the time derivative.  The TGV cases carry the
-    background pressure p0 = 71.4 whose gradient must cancel: the two sides
-    compute the metric terms independently, each to round-off (~1e-14
-    relative), and p0 times that difference, differentiated, is ~2e-11 against
-    |R| ~ 0.06 -- measured: the freestream residuals of the two sides differ by
-    2e-10 of |R| on the 3^3 mesh (at Ma = 1, p0 = 0.71, parity is 4e-12).
-    Hence 1e-9 there; 1e-12 where the background is O(1)."""
+    """one evaluation of the time derivative"""
     wl = _case(name)
     _say(f"[rhs parity] {name} E={wl.mesh.n_elems} N={wl.params['N']}")
     o = O.Oracle(wl.params, wl.mesh)
@@ -88,8 +96,8 @@ def test_rhs_parity(name):
     t = 0.13
     R_gpu = s.rhs(t)
     R_orc = o.rhs(wl.U0, t)
-    tol = 1e-9 if name.startswith("tgv") else 1e-12
-    _say(f"  rel L2 {rel(R_gpu, R_orc):.3e}")
+    tol = tgv_rhs_bound(wl.mesh.K[0]) if name.startswith("tgv") else 1e-12
+    _say(f"  rel L2 {rel(R_gpu, R_orc):.3e} (bound {tol:.1e})")
     assert rel(R_gpu, R_orc) <= tol, rel(R_gpu, R_orc)
 
 
@@ -148,8 +156,8 @@ def test_full_size_tgv_24cubed_one_step():
     s.set_state(wl.U0, 0.0)
     R_gpu = s.rhs(0.0)
     R_orc = o.rhs(wl.U0, 0.0)
-    _say(f"  rhs rel L2 {rel(R_gpu, R_orc):.3e}")
-    assert rel(R_gpu, R_orc) <= 1e-9
+    _say(f"  rhs rel L2 {rel(R_gpu, R_orc):.3e} (bound {tgv_rhs_bound(24):.1e})")
+    assert rel(R_gpu, R_orc) <= tgv_rhs_bound(24)
     del R_gpu, R_orc
     dt = s.stable_dt(0.9, 0.9)
     assert abs(dt / o.stable_dt(wl.U0) - 1.0) < 1e-12
@@ -223,3 +231,52 @@ def test_error_paths():
     with pytest.raises(P.DGError) as ei:
         s.advance(1, 1e-3)
     assert ei.value.code == -5
+
+
+def test_nonfinite_step_reported_and_recovery():
+    """check_finite names the first non-finite step and stops there; a good
+    state loaded afterwards steps exactly as a fresh solve (the RK register is
+    not read by the first stage, so the NaN it holds cannot leak)"""
+    import paper_2404_12703_amd as P
+    wl = W.mms_workload(K=2, N=3)
+    p = dict(wl.params)
+    p["check_finite"] = 1
+    o = O.Oracle(wl.params, wl.mesh)
+    dt = o.stable_dt(wl.U0)
+    s = _solver(p, wl.mesh)
+    U = wl.U0.copy()
+    U[0, 0, 0] = np.nan
+    s.set_state(U)
+    with pytest.raises(P.DGError) as ei:
+        s.advance(3, dt)
+    assert ei.value.code == -5
+    assert "step 1 of 3" in str(ei.value)
+    s.set_state(wl.U0, 0.0)
+    s.advance(2, dt)
+    assert rel(s.state(), o.advance(wl.U0, dt, 2)) <= 1e-12
+    # a host-staged evaluation between steps leaves the stepping unchanged too
+    s.set_state(wl.U0, 0.0)
+    s.rhs(0.0)
+    s.advance(2, dt)
+    assert rel(s.state(), o.advance(wl.U0, dt, 2)) <= 1e-12
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_checkpoint_resume_is_bitwise(scheme):
+    """advance(2n) equals advance(n), read the state out, load it into a new
+    solver, advance(n): bit for bit"""
+    wl = W.tgv_workload(K=3, N=5, rotate=True)
+    p = dict(wl.params)
+    p["time_scheme"] = scheme
+    a = _solver(p, wl.mesh)
+    a.set_state(wl.U0, 0.0)
+    dt = a.stable_dt()
+    a.advance(6, dt)
+    b = _solver(p, wl.mesh)
+    b.set_state(wl.U0, 0.0)
+    b.advance(3, dt)
+    mid = b.state()
+    c = _solver(p, wl.mesh)
+    c.set_state(mid, 3 * dt)
+    c.advance(3, dt)
+    assert np.array_equal(a.state(), c.state())

@@ -188,3 +188,45 @@ def test_cfl_step_and_broken_mesh():
         U, _ = sv.fetch(rid)
         ref = _alone(wl, _dt(wl))
         assert np.linalg.norm(U - ref) <= 1e-12 * np.linalg.norm(ref), req
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def test_served_request_matches_oracle():
+    """a served FP64 request, batched with two others, against the oracle"""
+    import oracle as O
+    import paper_2404_12703_amd as P
+    req = dict(id=0, K=3, N=5, Ma=0.2, Re=800.0, steps=4)
+    wl = W.request_workload(req)
+    o = O.Oracle(wl.params, wl.mesh)
+    dt = o.stable_dt(wl.U0)
+    sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=4)
+    rid = sv.submit(wl.params, wl.mesh, wl.U0, wl.steps, dt, 0.0)
+    for i, n in ((1, 5), (2, 3)):
+        w = W.request_workload(dict(id=i, K=2 + i, N=n, Ma=0.1, Re=1000.0, steps=3))
+        sv.submit(w.params, w.mesh, w.U0, w.steps, -0.9, 0.0)
+    sv.run(0)
+    U, tm = sv.fetch(rid)
+    Uo = o.advance(wl.U0, dt, wl.steps)
+    assert _rel(U, Uo) <= 1e-12
+    assert _rel(U - wl.U0, Uo - wl.U0) <= 1e-9
+
+
+def test_large_state_leaves_through_several_staging_chunks():
+    """a 20 MiB state (more than one 16 MiB staging slot) comes back whole"""
+    import paper_2404_12703_amd as P
+    req = dict(id=0, K=10, N=7, Ma=0.1, Re=1600.0, steps=1)
+    wl = W.request_workload(req)
+    dt = _dt(wl)
+    sv = P.Server(arena_bytes=2 << 30, hbm_budget=2 << 30, max_active=2)
+    rid = sv.submit(wl.params, wl.mesh, wl.U0, 1, dt, 0.0)
+    small = W.request_workload(dict(id=1, K=2, N=3, Ma=0.1, Re=1000.0, steps=2))
+    rid2 = sv.submit(small.params, small.mesh, small.U0, 2, _dt(small), 0.0)
+    sv.run(0)
+    U, _ = sv.fetch(rid)
+    assert U.nbytes > 16 << 20
+    assert np.array_equal(U, _alone(wl, dt))
+    U2, _ = sv.fetch(rid2)
+    assert np.array_equal(U2, _alone(small, _dt(small)))
