@@ -49,6 +49,66 @@ def algorithmic_bytes_per_dof(N: int, mixed: bool):
     return vol, surf
 
 
+# the paper's memory per DOF of its Navier-Stokes solver (Sec. 4.3, Table
+# tab:memory_requirements), KiB per DOF at N = 3, 5, 7 on its GPUs
+PAPER_KIB_PER_DOF = {3: 1.049, 5: 0.942, 7: 0.869}
+
+
+def memory_per_dof(P, W):
+    """device workspace bytes per DOF of one solve, per degree and form"""
+    out = []
+    for N in range(1, 10):
+        E = 4096
+        dof = E * (N + 1) ** 3
+        row = {"N": N}
+        for name, prm in (("fp64", W.params(N, riemann=1)), ("mixed", W.params(N, riemann=1, precision=1)),
+                          ("split_fp64", W.params(N, node_type=1, volume_flux=1)),
+                          ("ctgv_fp64", W.params(N, node_type=1, volume_flux=1, shock=1, viscosity=1)
+                           if 2 <= N <= 7 else None)):
+            if prm is None:
+                continue
+            row[name + "_B_per_dof"] = P.workspace_bytes(prm, E) / dof
+        if N in PAPER_KIB_PER_DOF:
+            row["paper_B_per_dof"] = PAPER_KIB_PER_DOF[N] * 1024
+        out.append(row)
+    return out
+
+
+def pid_sweep(P, W, Ks, steps, split):
+    """PID (s) against DOF on one GPU at N = 7 (Sec. 4.4, the one-GPU part of
+    the scaling figure): curved TGV boxes of K^3 elements; standard form on
+    Gauss nodes, or the split form on Gauss-Lobatto nodes"""
+    import torch
+    rows = []
+    for K in Ks:
+        if split:
+            wl = W.compressible_tgv_workload(K=K, N=7, curved=True)
+            wl.params = dict(wl.params, shock_capturing=0, time_scheme=0)
+        else:
+            wl = W.tgv_workload(K=K, N=7)
+        s = P.Solver(wl.params, wl.mesh)
+        s.set_state(wl.U0, 0.0)
+        dt = s.stable_dt(0.5, 0.5)
+        s.advance(2, dt)
+        s.synchronize()
+        n = max(2, min(steps, int(4e9 / (wl.dof * 5))))  # about half a second of work
+        t0 = time.perf_counter()
+        s.advance(n, dt)
+        s.synchronize()
+        el = time.perf_counter() - t0
+        rows.append({"K": K, "dof": wl.dof, "steps": n, "pid_s": el / (wl.dof * 5 * n),
+                     "value": wl.dof * 5 * n / el})
+        progress(f"  PID sweep {'split' if split else 'standard'} K={K}: {rows[-1]['pid_s']:.3e} s")
+        del s
+        torch.cuda.empty_cache()
+    return rows
+
+
+def progress(msg):
+    """a progress line on stderr (stdout carries the one JSON result line)"""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2404_12703_amd", "csrc")
@@ -139,13 +199,18 @@ def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30,
         arrivals = np.cumsum(g.exponential(1.0 / lam, size=nreq))
     arena = min(budget + (256 << 20), int(torch.cuda.mem_get_info()[0] * 0.8))
     sv = P.Server(arena_bytes=arena, hbm_budget=budget, max_active=max_active)
+    # the whole stream is submitted before the loop starts; arrival times are
+    # on the server clock, which starts with the loop
     ids = []
-    for r, ta in zip(base, arrivals):
+    for i, (r, ta) in enumerate(zip(base, arrivals)):
         wl = W.request_workload(r, precision=precision)
         ids.append(sv.submit(wl.params, wl.mesh, wl.U0, r["steps"], -0.9, float(ta)))
+        if (i + 1) % 128 == 0:
+            progress(f"  submitted {i + 1}/{nreq}")
     t0 = time.perf_counter()
     sv.run(0)
     makespan = time.perf_counter() - t0
+    progress(f"served {nreq} requests, load {load}, precision {precision}: {makespan:.1f} s")
     lat, ok = [], 0
     for rid in ids:
         _, tm = sv.fetch(rid)
@@ -204,11 +269,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--K", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the served stream")
+    ap.add_argument("--serve-requests", type=int, default=512, help="requests of the served stream")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed precision and latency")
     ap.add_argument("--only-main", action="store_true", help="time the main workload only (profiling runs)")
     ap.add_argument("--only-blast", action="store_true",
                     help="time the shock-capturing blast workload only (profiling runs of that path)")
+    ap.add_argument("--only-ctgv", action="store_true",
+                    help="time the supersonic split-form TGV only (profiling runs of that path)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -253,8 +320,24 @@ def main():
                           "k_volume_ms": pb["lift"][0] / pb["lift"][1], "k_surface_ms": pb["rhs"][0] / pb["rhs"][1],
                           "alpha_pos_fraction": float(np.mean(sbl.alpha() > 0))}), flush=True)
         return
+    if args.only_ctgv:
+        wc = W.compressible_tgv_workload(K=args.K, N=7, curved=True)
+        sc = P.Solver(wc.params, wc.mesh)
+        sc.set_state(wc.U0, 0.0)
+        dtc = sc.stable_dt(wc.cfl, wc.cfl)
+        sc.advance(args.warmup, dtc)
+        sc.synchronize()
+        t0 = time.perf_counter()
+        sc.advance(args.steps, dtc)
+        sc.synchronize()
+        elc = time.perf_counter() - t0
+        print(json.dumps({"workload": "supersonic TGV 24^3 N=7 Lobatto, split form, 14-stage RK, FP64",
+                          "steps": args.steps, "value": wc.dof * 14 * args.steps / elc, "unit": "DOF*stage/s",
+                          "alpha_pos_fraction": float(np.mean(sc.alpha() > 0))}), flush=True)
+        return
     wl = W.tgv_workload(K=args.K, N=7, steps=args.steps)
     N = 7
+    progress(f"main workload: {wl.dof} DOF, {args.steps} steps")
     s, dt, el, prof = time_solver(P, wl, args.steps, args.warmup, profile_pass=not args.only_main)
     value = wl.dof * 5 * args.steps / el
     line = {
@@ -316,18 +399,32 @@ def main():
     if not args.no_extras and not args.only_main:
         # mixed precision against FP64 on the 32^3 mesh: 500 steps with the same dt,
         # five full solves each; E_k and the state of the last solves compared
+        progress("mixed precision against FP64, 32^3, 500 steps x 5 solves each")
         wd = W.tgv_workload(K=32, N=7, precision=0)
         wm = W.tgv_workload(K=32, N=7, precision=1)
         std, sd, Ud = solve_latency(P, wd, 500, 5)
         stm, sm, Um = solve_latency(P, wm, 500, 5, dt=std["dt"])
         Id, Im = sd.integrals(), sm.integrals()
+        # per-kernel times of the mixed form (HIP events on its stream)
+        sm.profile(True)
+        sm.advance(10, std["dt"])
+        pm = sm.profile_read()
+        sm.profile(False)
+        vbm, sbm = algorithmic_bytes_per_dof(7, True)
+        mixed_k = {}
+        for key, name, b in (("lift", "k_volume", vbm), ("rhs", "k_surface", sbm)):
+            t = pm[key][0] / pm[key][1] * 1e-3
+            mixed_k[name] = {"avg_ms": t * 1e3, "alg_bytes_per_dof": b, "alg_GBs": b * wm.dof / t / 1e9,
+                             "frac": b * wm.dof / t / 1e9 / HBM_PEAK_GBS}
         line["mixed_tgv32"] = {
             "dof": wd.dof, "steps": 500, "fp64": std, "mixed": stm,
             "speedup": std["p50_s"] / stm["p50_s"],
+            "kernels": mixed_k,
             "ek_rel_err": abs(Im[5] - Id[5]) / abs(Id[5]),
             "state_rel_l2": float(torch.linalg.norm(Um - Ud) / torch.linalg.norm(Ud))}
         del sd, sm, Ud, Um
         torch.cuda.empty_cache()
+        progress("latency of whole solves")
         st, s2, _ = solve_latency(P, W.tgv_workload(K=args.K, N=7), args.steps, 20)
         line["latency_tgv24"] = st
         del s2
@@ -335,6 +432,7 @@ def main():
         line["latency_mms"] = st
         del s1
         # the shock-capturing workload: 32^3 Lobatto N=5, indicator + FV blend
+        progress("blast 32^3, 200 steps x 5 solves")
         wb = W.blast_workload(K=32, N=5)
         st, sbl, _ = solve_latency(P, wb, 200, 5)
         sbl.set_state(wb.U0, 0.0)
@@ -343,10 +441,44 @@ def main():
         line["blast32"] = st
         del sbl
         torch.cuda.empty_cache()
+        # the supersonic Taylor-Green vortex: split form (Pirozzoli), Sutherland,
+        # indicator + FV blend, fourteen-stage RK; 24^3 curved, N = 7 Lobatto
+        progress("supersonic split-form TGV")
+        wc = W.compressible_tgv_workload(K=args.K, N=7, curved=True)
+        sc = P.Solver(wc.params, wc.mesh)
+        sc.set_state(wc.U0, 0.0)
+        dtc = sc.stable_dt(wc.cfl, wc.cfl)
+        sc.advance(2, dtc)
+        sc.synchronize()
+        nst = 20
+        t0 = time.perf_counter()
+        sc.advance(nst, dtc)
+        sc.synchronize()
+        elc = time.perf_counter() - t0
+        sc.profile(True)
+        sc.advance(2, dtc)
+        pc = sc.profile_read()
+        sc.profile(False)
+        line["ctgv24_split"] = {
+            "workload": "supersonic TGV Ma 1.25 Re 1600, curved 24^3, N=7 Lobatto, split form + Sutherland + "
+                        "indicator/FV blend + 14-stage RK, FP64",
+            "dof": wc.dof, "steps": nst, "stages_per_step": 14, "dt": dtc,
+            "value": wc.dof * 14 * nst / elc, "unit": "DOF*stage/s", "pid_s": elc / (wc.dof * 14 * nst),
+            "k_volume_ms": pc["lift"][0] / pc["lift"][1], "k_surface_ms": pc["rhs"][0] / pc["rhs"][1],
+            "alpha_pos_fraction": float(np.mean(sc.alpha() > 0)),
+            "eps_S_eps_D": [float(x) for x in sc.dissipation()], "finite": bool(np.isfinite(sc.integrals()).all())}
+        del sc
+        torch.cuda.empty_cache()
         line["served"] = [served(P, W, args.serve_requests, 0, value, load=ld, precision=0)
                           for ld in (0.5, 0.8, 1.2, None)]
         line["served"].append(served(P, W, args.serve_requests, 0, value, load=0.8, precision=1))
+        progress("PID sweep")
+        line["pid_sweep_n7"] = {
+            "standard_gauss": pid_sweep(P, W, (3, 4, 6, 8, 12, 16, 24, 32, 40, 48, 58), 20, split=False),
+            "split_lobatto": pid_sweep(P, W, (3, 4, 6, 8, 12, 16, 24, 32, 40, 48, 58), 20, split=True)}
+        line["memory_per_dof"] = memory_per_dof(P, W)
     if not args.no_cpu and not args.only_main:
+        progress("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(W.tgv_workload(K=args.K, N=7, steps=1), args.K)
     print(json.dumps(line), flush=True)
 

@@ -220,8 +220,8 @@ typedef struct dg_server dg_server;
 enum { DG_REQ_QUEUED = 0, DG_REQ_RUNNING = 1, DG_REQ_DONE = 2, DG_REQ_FAILED = 3 };
 
 typedef struct dg_timing {
-  double t_arrival; /* given at submit (seconds, caller's clock)          */
-  double t_admit;   /* server clock (seconds since dg_server_create) when admitted */
+  double t_arrival; /* given at submit (seconds on the server clock)      */
+  double t_admit;   /* server clock (seconds since the first dg_server_run) when admitted */
   double t_done;    /* server clock when the result was copied out        */
   int32_t state;    /* DG_REQ_*                                           */
   int32_t reserved;
@@ -239,8 +239,9 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
 /* Queue one solve: parameters, mesh, initial state (host [5][E][(N+1)^3]),
  * n_steps of size dt.  dt < 0 asks for the stable step of dg_stable_dt with
  * CFL = DFL = -dt on the initial state, evaluated in FP64 on the host when
- * the request is prepared.  All host data is copied.  t_arrival: the caller's
- * clock, seconds since server creation; the request becomes eligible for
+ * the request is prepared.  All host data is copied.  t_arrival: seconds on
+ * the server clock, which starts at the first dg_server_run call (so a
+ * stream can be submitted up front); the request becomes eligible for
  * admission once the server clock passes it.  Once a request has arrived, a
  * thread of the server builds its geometry and metrics while the serving loop
  * runs, reusing those of an identical mesh and set-up seen before (up to

@@ -239,9 +239,14 @@ struct dg_server {
   GeoCache geo;  // the preparation thread's
   std::vector<int64_t> active;
   int64_t next_id = 1;
+  // the server clock starts at the first dg_server_run call (0 before it)
   std::chrono::steady_clock::time_point t0;
+  std::atomic<bool> started{false};
   bool broken = false;
-  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+  double now() const {
+    if (!started.load(std::memory_order_acquire)) return 0.0;
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
 };
 
 namespace {
@@ -640,7 +645,6 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
       return fail(DG_EDEVICE, std::string("server streams: ") + hipGetErrorString(e));
     }
   }
-  sv->t0 = std::chrono::steady_clock::now();
   sv->prep_thread = std::thread(prep_loop, sv.get());
   *out = sv.release();
   return DG_OK;
@@ -686,6 +690,14 @@ dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, 
 dg_status dg_server_run(dg_server *sv, int32_t max_ticks) {
   if (!sv) return fail(DG_EINVAL, "server is NULL");
   if (sv->broken) return fail(DG_ESTATE, "server unusable after a device error");
+  if (!sv->started.load(std::memory_order_relaxed)) {
+    {
+      std::lock_guard<std::mutex> lk(sv->prep_mu);
+      sv->t0 = std::chrono::steady_clock::now();
+      sv->started.store(true, std::memory_order_release);
+    }
+    sv->prep_cv.notify_all();  // arrival times are on the clock that starts now
+  }
   int ticks = 0;
   for (;;) {
     dg_status rc = admit(sv);

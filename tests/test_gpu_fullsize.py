@@ -1,8 +1,8 @@
 """GPU parity at the benchmark workloads' full sizes, over many steps: the
 curved Taylor-Green vortex (24^3 elements, N = 7, 7.1M DOF) after 100 steps
 against the oracle to 1e-10, and the shock-capturing blast (32^3 elements,
-N = 5 Lobatto, 7.1M DOF) over 20 steps with the blending factors of both
-sides compared at the end.  The oracle runs on every host core in chunks of
+N = 5 Lobatto, 7.1M DOF, Euler) over 20 steps at CFL 0.9 with the blending
+factors of both sides compared at the end.  The oracle runs on every host core in chunks of
 steps, printing each chunk (a few minutes in all)."""
 import sys
 import time
@@ -74,6 +74,8 @@ def test_blast_32cubed_twenty_steps():
     _say(f"  blended {np.mean(ao > 0):.4f}, flips {flips}, max |dalpha| {np.abs(ag - ao).max():.2e}, "
          f"state {e:.3e}, change {ed:.3e}")
     assert flips == 0
-    assert np.abs(ag - ao).max() <= 1e-10
+    # the logistic map's slope s/(4T) = 3e4 at this threshold (T = 7.6e-5)
+    # carries the round-off of the modal energy fraction (~1e-14) into alpha
+    assert np.abs(ag - ao).max() <= 1e-9
     assert e <= 1e-11
     assert ed <= 1e-9

@@ -155,8 +155,10 @@ def test_arrivals_are_admitted_while_others_run():
     sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=8)
     ids = []
     for i, (req, wl) in enumerate(reqs):
-        wl.steps = 40
-        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, 40, _dt(wl), 0.0 if i < 3 else 0.02))
+        # the early requests run long enough (about 0.1 s) for the late ones,
+        # arriving 5 ms after the loop starts, to join them
+        n = 300 if i < 3 else 40
+        ids.append(sv.submit(wl.params, wl.mesh, wl.U0, n, _dt(wl), 0.0 if i < 3 else 0.005))
     sv.run(0)
     tms = [sv.fetch(r)[1] for r in ids]
     first_done = min(t["t_done"] for t in tms[:3])
