@@ -190,6 +190,17 @@ dg_status dg_integrals(dg_solver *s, double out[7]);
  * (synchronises).  DG_EINVAL without the viscous operator. */
 dg_status dg_dissipation(dg_solver *s, double out[2]);
 
+/* dg_dissipation for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and the same result, but the per-element partial sums go
+ * to a file-scope device array of the library (6 MiB per GPU, held until the
+ * process ends) instead of the solver's workspace.  At most 262144 elements
+ * (DG_EINVAL above); the solver's workspace must be on the current device.
+ * The first call on a device looks the array's address up once.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU race.
+ * Makes no hipMalloc/hipFree call; synchronises the solver's stream. */
+dg_status dg_dissipation_noalloc(dg_solver *s, double out[2]);
+
 /* Wait for all work the solver enqueued on its stream (the host side of the
  * asynchronous stage launches of Sec. 3.2). */
 dg_status dg_synchronize(dg_solver *s);

@@ -78,6 +78,7 @@ def lib():
             "dg_integrals": (i32, [vp, vp]),
             "dg_synchronize": (i32, [vp]),
             "dg_dissipation": (i32, [vp, vp]),
+            "dg_dissipation_noalloc": (i32, [vp, vp]),
             "dg_destroy": (None, [vp]),
             "dg_profile_enable": (i32, [vp, i32]),
             "dg_profile_read": (i32, [vp, i32, vp, vp]),
@@ -242,6 +243,12 @@ class Solver:
         """(eps_S, eps_D) of the current state"""
         out = np.zeros(2)
         _check(lib().dg_dissipation(self._h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def dissipation_noalloc(self):
+        """(eps_S, eps_D) through the entry point that allocates nothing"""
+        out = np.zeros(2)
+        _check(lib().dg_dissipation_noalloc(self._h, C.c_void_p(out.ctypes.data)))
         return out
 
     def profile(self, on: bool):

@@ -159,6 +159,8 @@ hipError_t launch_integrals(int N, const View<real> &v, double *scratch, int nbl
 // sets *flag to 1 if U[0..count) holds a NaN or Inf (leaves it otherwise)
 hipError_t launch_finite(const double *U, int64_t count, int *flag, hipStream_t st);
 hipError_t launch_zero_int(int *p, int count, hipStream_t st);
+// out[c] = sum over e < E of in[3 e + c], c = 0..2, in a fixed order
+hipError_t launch_sum3(const double *in, int64_t E, double *out, hipStream_t st);
 hipError_t launch_cast(const double *src, float *dst, int64_t count, hipStream_t st);
 
 }  // namespace dg

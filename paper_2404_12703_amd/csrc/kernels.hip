@@ -112,6 +112,31 @@ __global__ void __launch_bounds__(256) k_finite(const double *U, int64_t count, 
   if (threadIdx.x == 0 && bad) atomicOr(flag, 1);
 }
 
+// sums of the per-element triples in[3 e + c] over e < E into out[0..2], in a
+// fixed order (one workgroup: strided partial sums per thread, then a tree),
+// so the result does not depend on the launch
+__global__ void __launch_bounds__(1024) k_sum3(const double *in, int64_t E, double *out) {
+  __shared__ double s[3][1024];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t e = threadIdx.x; e < E; e += 1024) {
+    a0 += in[3 * e];
+    a1 += in[3 * e + 1];
+    a2 += in[3 * e + 2];
+  }
+  s[0][threadIdx.x] = a0;
+  s[1][threadIdx.x] = a1;
+  s[2][threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
 __global__ void __launch_bounds__(256) k_zero_int(int *p, int count) {
   for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) p[t] = 0;
 }
@@ -189,6 +214,11 @@ hipError_t launch_integrals(int N, const View<real> &v, double *scratch, int nbl
 
 hipError_t launch_finite(const double *U, int64_t count, int *flag, hipStream_t st) {
   k_finite<<<256, 256, 0, st>>>(U, count, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum3(const double *in, int64_t E, double *out, hipStream_t st) {
+  k_sum3<<<1, 1024, 0, st>>>(in, E, out);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -371,6 +372,64 @@ hipError_t solver_advance(dg_solver *s, int nsteps, double dt) {
   return s->mixed ? advance_impl<float>(s, nsteps, dt) : advance_impl<double>(s, nsteps, dt);
 }
 
+// One volume sweep of the current state with the dissipation sums on (stage
+// temporaries only: the volume integral and the viscous face fluxes), the
+// per-element sums into diag[E][3], their fixed-order total into sums[3],
+// and the two rates of Sec. 5.2 on the host.
+hipError_t dissipation_sweep(dg_solver *s, double *diag, double *sums, double out[2]) {
+  hipError_t e = hipSuccess;
+  auto sweep = [&](auto &v) {
+    using real = typename std::remove_reference<decltype(v)>::type::value_type;
+    v.t = s->t;
+    v.cur = s->cur;
+    v.bpar = s->bpar;
+    v.R = nullptr;
+    if (!s->traces_valid) {
+      e = run_kernel<real>(s, K_TRACE, 0, v);
+      if (e != hipSuccess) return;
+      s->traces_valid = true;
+    }
+    v.diag = diag;
+    e = run_kernel<real>(s, K_DIAG, 0, v);
+    v.diag = nullptr;
+  };
+  if (s->mixed) sweep(s->vf);
+  else sweep(s->vd);
+  double h[3] = {0.0, 0.0, 0.0};
+  if (e == hipSuccess) e = launch_sum3(diag, s->E, sums, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return e;
+  out[0] = h[0] / h[2];
+  out[1] = 4.0 / 3.0 * h[1] / h[2];
+  return hipSuccess;
+}
+
+// The allocation-free dissipation entry point's device memory: a file-scope
+// array on every GPU the library runs on, held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): it takes the array's device address from
+// hipGetSymbolAddress, once per device with that device current, and uses
+// that address everywhere.  Calls that overlap on one GPU share the array and
+// race.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[3 * kStaticElems + 8];
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(int dev, double **ptr) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace dg
 
 using namespace dg;
@@ -557,39 +616,34 @@ dg_status dg_dissipation(dg_solver *s, double out[2]) {
   CHECK_SOLVER(s);
   if (!out) return fail(DG_EINVAL, "out is NULL");
   if (!s->p.viscous) return fail(DG_EINVAL, "the dissipation rates need the viscous operator");
-  // one volume sweep of the current state with the per-element sums on; it
-  // writes only the stage temporaries (volume integral, viscous face fluxes)
   double *d = (double *)((char *)s->ws + s->L.diag);
-  hipError_t e = hipSuccess;
-  auto sweep = [&](auto &v) {
-    using real = typename std::remove_reference<decltype(v)>::type::value_type;
-    v.t = s->t;
-    v.cur = s->cur;
-    v.bpar = s->bpar;
-    v.R = nullptr;
-    if (!s->traces_valid) {
-      e = run_kernel<real>(s, K_TRACE, 0, v);
-      if (e != hipSuccess) return;
-      s->traces_valid = true;
-    }
-    v.diag = d;
-    e = run_kernel<real>(s, K_DIAG, 0, v);
-    v.diag = nullptr;
-  };
-  if (s->mixed) sweep(s->vf);
-  else sweep(s->vd);
-  std::vector<double> h(3 * (size_t)s->E);
-  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost, s->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  double *sums = (double *)((char *)s->ws + s->L.scratch);
+  hipError_t e = dissipation_sweep(s, d, sums, out);
   if (e != hipSuccess) return device_error(s, e, "dg_dissipation");
-  double sS = 0.0, sD = 0.0, vol = 0.0;
-  for (int64_t el = 0; el < s->E; ++el) {
-    sS += h[3 * el];
-    sD += h[3 * el + 1];
-    vol += h[3 * el + 2];
-  }
-  out[0] = sS / vol;
-  out[1] = 4.0 / 3.0 * sD / vol;
+  return DG_OK;
+}
+
+dg_status dg_dissipation_noalloc(dg_solver *s, double out[2]) {
+  CHECK_SOLVER(s);
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  if (!s->p.viscous) return fail(DG_EINVAL, "the dissipation rates need the viscous operator");
+  if (s->E > kStaticElems)
+    return fail(DG_EINVAL, "dg_dissipation_noalloc takes at most " + std::to_string(kStaticElems) +
+                               " elements (its static device array); this solve has " + std::to_string(s->E));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(nullptr, e, "dg_dissipation_noalloc");
+  hipPointerAttribute_t at;
+  e = hipPointerGetAttributes(&at, s->ws);
+  if (e != hipSuccess) return device_error(nullptr, e, "dg_dissipation_noalloc workspace attributes");
+  if (at.device != dev)
+    return fail(DG_EINVAL, "dg_dissipation_noalloc: the solver's workspace is on device " + std::to_string(at.device) +
+                               ", the current device is " + std::to_string(dev));
+  double *base = nullptr;
+  e = static_scratch(dev, &base);
+  if (e != hipSuccess) return device_error(nullptr, e, "dg_dissipation_noalloc scratch address");
+  e = dissipation_sweep(s, base, base + 3 * kStaticElems, out);
+  if (e != hipSuccess) return device_error(s, e, "dg_dissipation_noalloc");
   return DG_OK;
 }
 

@@ -11,6 +11,9 @@
 namespace dg {
 
 constexpr int kRedBlocks = 1024;  // blocks of the reduction kernels
+// elements the allocation-free dissipation call takes (its static device
+// array holds 3 doubles per element: 6 MiB)
+constexpr int64_t kStaticElems = int64_t(1) << 18;
 
 // byte offsets of every array inside the caller's workspace (SIZE_MAX: absent)
 struct Layout {
