@@ -216,8 +216,9 @@ def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30,
         _, tm = sv.fetch(rid)
         ok += tm["state"] == P.REQ_DONE
         lat.append(tm["t_done"] - tm["t_arrival"])
+    stats = sv.stats()
     sv.close()
-    return dict(requests=nreq, done=ok, load=("all at t=0" if load is None else load), precision=precision,
+    return dict(stats=stats, requests=nreq, done=ok, load=("all at t=0" if load is None else load), precision=precision,
                 value=float(np.sum(work)) / makespan, unit="DOF*stage/s",
                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 makespan_s=makespan, budget_GB=budget / 2 ** 30)
@@ -276,6 +277,8 @@ def main():
                     help="time the shock-capturing blast workload only (profiling runs of that path)")
     ap.add_argument("--only-ctgv", action="store_true",
                     help="time the supersonic split-form TGV only (profiling runs of that path)")
+    ap.add_argument("--only-served", action="store_true",
+                    help="the served stream only (FP64, load 0.8 and all at t = 0), with the loop statistics")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -334,6 +337,14 @@ def main():
         print(json.dumps({"workload": "supersonic TGV 24^3 N=7 Lobatto, split form, 14-stage RK, FP64",
                           "steps": args.steps, "value": wc.dof * 14 * args.steps / elc, "unit": "DOF*stage/s",
                           "alpha_pos_fraction": float(np.mean(sc.alpha() > 0))}), flush=True)
+        return
+    if args.only_served:
+        wl = W.tgv_workload(K=args.K, N=7, steps=10)
+        _, _, el, _ = time_solver(P, wl, 10, 2, profile_pass=False)
+        rate = wl.dof * 5 * 10 / el
+        out = {"single_solve_value": rate,
+               "served": [served(P, W, args.serve_requests, 0, rate, load=ld, precision=0) for ld in (None, 0.8)]}
+        print(json.dumps(out), flush=True)
         return
     wl = W.tgv_workload(K=args.K, N=7, steps=args.steps)
     N = 7

@@ -271,6 +271,17 @@ dg_status dg_server_poll(dg_server *sv, int64_t req_id, int32_t *state);
 /* Copy a finished request's state ([5][E][(N+1)^3] doubles) and timing to the host. */
 dg_status dg_server_fetch(dg_server *sv, int64_t req_id, double *U_host, dg_timing *timing);
 
+/* Loop statistics since creation: out[0] ticks, out[1] mean active requests
+ * per tick, host seconds spent in out[2] admission (set-up uploads), out[3]
+ * tick issue (launches and descriptor copies, out[5] included), out[4]
+ * retirement, out[5] waiting for the GPU to free a descriptor slot, out[6]
+ * waiting with nothing to run; out[7] bytes uploaded at admission; out[8]
+ * geometry blocks uploaded and out[9] admissions that found their mesh's
+ * geometry resident (the arena keeps each mesh's read-only metrics, normals
+ * and connectivity after its last request, shared by the requests of that
+ * mesh, until the memory is needed). */
+dg_status dg_server_stats(dg_server *sv, double out[10]);
+
 void dg_server_destroy(dg_server *sv);
 
 #ifdef __cplusplus

@@ -87,6 +87,7 @@ def lib():
             "dg_server_run": (i32, [vp, i32]),
             "dg_server_poll": (i32, [vp, i64, C.POINTER(i32)]),
             "dg_server_fetch": (i32, [vp, i64, vp, C.POINTER(dg_timing)]),
+            "dg_server_stats": (i32, [vp, vp]),
             "dg_server_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
@@ -305,6 +306,13 @@ class Server:
         st = C.c_int32(0)
         _check(lib().dg_server_poll(self._h, int(rid), C.byref(st)))
         return st.value
+
+    def stats(self):
+        out = np.zeros(10)
+        _check(lib().dg_server_stats(self._h, C.c_void_p(out.ctypes.data)))
+        keys = ("ticks", "mean_active", "host_admit_s", "host_tick_s", "host_retire_s", "gpu_wait_s", "idle_s",
+                "upload_bytes", "geometry_uploads", "geometry_hits")
+        return dict(zip(keys, out.tolist()))
 
     def fetch(self, rid: int):
         out = np.empty(self._shapes[rid])

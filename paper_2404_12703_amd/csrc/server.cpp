@@ -44,6 +44,10 @@ constexpr int kDescSlots = 64;  // ring of descriptor uploads in flight
 // each other's tails.  Each tick forks from the server's stream and joins it.
 constexpr int kGroupStreams = 3;
 constexpr int kPrepAhead = 16;  // requests at the head of the queue prepared ahead of admission
+// pinned host memory the preparation thread stages initial states in, so
+// admission uploads them asynchronously (a state that does not fit goes from
+// pageable memory at admission)
+constexpr size_t kUpStageBytes = size_t(512) << 20;
 constexpr size_t kGeoCacheBytes = size_t(4) << 30;  // host memory of the geometry cache
 enum { PREP_WAITING = 0, PREP_RUNNING = 1, PREP_READY = 2, PREP_FAILED = 3 };
 
@@ -60,9 +64,12 @@ struct Request {
   double dt = 0.0;
   double t_arrival = 0.0, t_admit = -1.0, t_done = -1.0;
   int32_t state = DG_REQ_QUEUED;
-  // while active
+  // while active: the request's own block (state and temporaries) and the
+  // shared geometry block of its mesh
   size_t off = 0, bytes = 0;
-  Layout L{};
+  Layout L{};   // LAYOUT_STATE
+  Layout Lg{};  // LAYOUT_GEOMETRY
+  const HostSetup *geo_key = nullptr;
   View<double> vd{};
   View<float> vf{};
   int step = 0, stage = 0, cur = 0, bpar = 0;  // bpar: alternates over surface sweeps
@@ -71,6 +78,7 @@ struct Request {
   // host set-up, made by the preparation thread once the request has arrived;
   // kept until its upload has landed
   std::shared_ptr<const HostSetup> host;
+  size_t up_off = SIZE_MAX;  // the initial state's place in the pinned staging area, if staged
   std::atomic<int> prep{PREP_WAITING};
   std::string prep_err;
   hipEvent_t ready = nullptr;  // set-up copies done
@@ -228,7 +236,23 @@ struct dg_server {
   hipStream_t gst[kGroupStreams] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kGroupStreams] = {};
   StageSlot slots[kStageSlots];
+  // geometry blocks resident in the arena, one per distinct set-up (mesh,
+  // degree, node type, precision), shared by the requests that use it; kept
+  // after their last request retires and evicted least recently used when
+  // memory is needed
+  struct DevGeo {
+    std::shared_ptr<const HostSetup> hs;  // holds the key's identity while the block lives
+    size_t off = 0, bytes = 0;
+    int refs = 0;
+    uint64_t used = 0;
+  };
+  std::map<const HostSetup *, DevGeo> dgeo;
+  uint64_t dgeo_clock = 0;
+  int64_t st_geo_hits = 0, st_geo_uploads = 0;
   std::vector<hipEvent_t> ev_free;  // events of admitted requests, reused
+  char *up_host = nullptr;          // kUpStageBytes of pinned memory
+  Arena up_alloc;                   // its allocator, shared by the preparation thread and the loop
+  std::mutex up_mu;
   // reqs and queue are shared with the preparation thread: changed under prep_mu
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::deque<int64_t> queue;
@@ -243,6 +267,9 @@ struct dg_server {
   std::chrono::steady_clock::time_point t0;
   std::atomic<bool> started{false};
   bool broken = false;
+  // loop statistics (dg_server_stats)
+  int64_t st_ticks = 0, st_active_sum = 0;
+  double st_admit = 0.0, st_tick = 0.0, st_retire = 0.0, st_gpu_wait = 0.0, st_idle = 0.0, st_upload_bytes = 0.0;
   double now() const {
     if (!started.load(std::memory_order_acquire)) return 0.0;
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -302,7 +329,19 @@ void prep_loop(dg_server *sv) {
     }
     double dt = next->dt;
     if (rc == DG_OK && dt < 0.0) dt = host_stable_dt(next->p, next->E, *hs, next->U0.data(), -dt);
+    size_t up = SIZE_MAX;
+    if (rc == DG_OK && sv->up_host) {
+      const size_t bytes = next->U0.size() * 8;
+      bool got;
+      {
+        std::lock_guard<std::mutex> ul(sv->up_mu);
+        got = sv->up_alloc.alloc(bytes, up);
+      }
+      if (got) std::memcpy(sv->up_host + up, next->U0.data(), bytes);
+      else up = SIZE_MAX;
+    }
     lk.lock();
+    next->up_off = up;
     if (rc == DG_OK) {
       next->dt = dt;
       next->host = std::move(hs);
@@ -311,6 +350,20 @@ void prep_loop(dg_server *sv) {
       next->prep_err = err;
       next->prep.store(PREP_FAILED, std::memory_order_release);
     }
+  }
+}
+
+// take arena memory, evicting resident geometry blocks that no active
+// request uses (least recently used first) until it fits
+bool alloc_evicting(dg_server *sv, size_t bytes, size_t &off) {
+  for (;;) {
+    if (sv->alloc.alloc(bytes, off)) return true;
+    auto lru = sv->dgeo.end();
+    for (auto it = sv->dgeo.begin(); it != sv->dgeo.end(); ++it)
+      if (it->second.refs == 0 && (lru == sv->dgeo.end() || it->second.used < lru->second.used)) lru = it;
+    if (lru == sv->dgeo.end()) return false;
+    sv->alloc.release(lru->second.off, lru->second.bytes);
+    sv->dgeo.erase(lru);
   }
 }
 
@@ -339,21 +392,50 @@ dg_status admit(dg_server *sv) {
       r.t_done = now;
       continue;
     }
+    // the geometry block of its set-up: resident already, or uploaded now
+    auto git = sv->dgeo.find(r.host.get());
+    const bool geo_new = git == sv->dgeo.end();
+    size_t goff = 0;
+    if (geo_new && !alloc_evicting(sv, r.Lg.total, goff)) break;  // wait for memory to free up
     size_t off;
-    if (!sv->alloc.alloc(r.L.total, off)) break;  // wait for memory to free up
+    if (!alloc_evicting(sv, r.L.total, off)) {
+      if (geo_new) sv->alloc.release(goff, r.Lg.total);
+      break;
+    }
     {
       std::lock_guard<std::mutex> lk(sv->prep_mu);
       sv->queue.pop_front();
     }
     sv->prep_cv.notify_one();  // the next request in line may be prepared now
+    hipError_t e = hipSuccess;
+    if (geo_new) {
+      dg_server::DevGeo g;
+      g.hs = r.host;
+      g.off = goff;
+      g.bytes = r.Lg.total;
+      e = upload_geometry(r.p, *r.host, sv->arena + goff, r.Lg, sv->cst);
+      sv->st_upload_bytes += (double)r.host->bytes();
+      ++sv->st_geo_uploads;
+      git = sv->dgeo.emplace(r.host.get(), std::move(g)).first;
+    } else {
+      ++sv->st_geo_hits;
+    }
+    git->second.refs += 1;
+    git->second.used = ++sv->dgeo_clock;
+    r.geo_key = r.host.get();
     r.off = off;
     r.bytes = r.L.total;
     void *base = sv->arena + off;
     fill_view(r.vd, base, r.L, r.p, r.E);
     fill_view(r.vf, base, r.L, r.p, r.E);
-    hipError_t e = setup_device(r.p, *r.host, base, r.L, sv->cst);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync((char *)base + r.L.U, r.U0.data(), r.U0.size() * 8, hipMemcpyHostToDevice, sv->cst);
+    attach_geometry(r.vd, sv->arena + git->second.off, r.Lg);
+    attach_geometry(r.vf, sv->arena + git->second.off, r.Lg);
+    if (e == hipSuccess) e = hipMemsetAsync(base, 0, r.L.total, sv->cst);
+    if (e == hipSuccess) {
+      const void *src = r.up_off != SIZE_MAX ? (const void *)(sv->up_host + r.up_off) : (const void *)r.U0.data();
+      e = hipMemcpyAsync((char *)base + r.L.U, src, r.U0.size() * 8, hipMemcpyHostToDevice, sv->cst);
+    }
+    sv->st_upload_bytes += (double)(r.U0.size() * 8);
     if (e == hipSuccess) {
       if (!sv->ev_free.empty()) {
         r.ready = sv->ev_free.back();
@@ -421,7 +503,9 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
   sv->desc_next = (sv->desc_next + 1) % kDescSlots;
   // the kernel that last read this slot is done, so its host mirror and device
   // copy may be rewritten (that kernel may have run on another stream)
+  const auto w0 = std::chrono::steady_clock::now();
   hipError_t e = hipEventSynchronize(sv->desc_ev[slot]);
+  sv->st_gpu_wait += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
   if (e != hipSuccess) return server_fail(sv, e, "descriptor ring");
   char *h = sv->desc_host[slot];
   View<real> *views = (View<real> *)h;
@@ -510,6 +594,14 @@ dg_status tick(dg_server *sv) {
   return DG_OK;
 }
 
+// give a staged initial state's pinned memory back (its upload has landed)
+void release_upload(dg_server *sv, Request &r) {
+  if (r.up_off == SIZE_MAX) return;
+  std::lock_guard<std::mutex> ul(sv->up_mu);
+  sv->up_alloc.release(r.up_off, r.U0.size() * 8);
+  r.up_off = SIZE_MAX;
+}
+
 // Copy finished requests out through the staging slots; release a request's
 // memory once its whole state has landed on the host.
 dg_status retire(dg_server *sv) {
@@ -564,7 +656,10 @@ dg_status retire(dg_server *sv) {
       if (r.ready) sv->ev_free.push_back(r.ready);
       r.ready = nullptr;
       r.host.reset();
+      release_upload(sv, r);  // its upload has landed: the copy-out followed it on the stream
       sv->alloc.release(r.off, r.bytes);
+      sv->dgeo.at(r.geo_key).refs -= 1;  // the block stays resident for the next request of this mesh
+      r.geo_key = nullptr;
       r.state = r.bad ? DG_REQ_FAILED : DG_REQ_DONE;
       r.t_done = sv->now();
       continue;
@@ -572,6 +667,7 @@ dg_status retire(dg_server *sv) {
     // the host set-up and initial state can go once their uploads have landed
     if (r.host && r.ready && hipEventQuery(r.ready) == hipSuccess) {
       r.host.reset();
+      release_upload(sv, r);
       std::vector<double>().swap(r.U0);
     }
     keep.push_back(id);
@@ -607,6 +703,10 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
     if (e == hipSuccess) e = hipEventRecord(sv->desc_ev[s], sv->st);
     if (e != hipSuccess) return fail(DG_EDEVICE, std::string("server set-up: ") + hipGetErrorString(e));
   }
+  if (hipHostMalloc((void **)&sv->up_host, kUpStageBytes, hipHostMallocDefault) == hipSuccess)
+    sv->up_alloc.init(0, kUpStageBytes);
+  else
+    sv->up_host = nullptr;  // no staging area: initial states go from pageable memory
   for (StageSlot &sl : sv->slots) {
     hipError_t e = hipHostMalloc((void **)&sl.host, kStageChunk + 256, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
@@ -619,6 +719,7 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
         if (sv->desc_host[q]) (void)hipHostFree(sv->desc_host[q]);
         if (sv->desc_ev[q]) (void)hipEventDestroy(sv->desc_ev[q]);
       }
+      if (sv->up_host) (void)hipHostFree(sv->up_host);
       return fail(DG_EDEVICE, std::string("server staging: ") + hipGetErrorString(e));
     }
   }
@@ -642,6 +743,7 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
         (void)hipHostFree(t.host);
         (void)hipEventDestroy(t.ev);
       }
+      if (sv->up_host) (void)hipHostFree(sv->up_host);
       return fail(DG_EDEVICE, std::string("server streams: ") + hipGetErrorString(e));
     }
   }
@@ -666,8 +768,9 @@ dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, 
   r->p = *p;
   r->E = m->n_elems;
   r->n_geo = m->n_geo;
-  r->L = make_layout(*p, r->E);
-  if (r->L.total > sv->budget) return fail(DG_EBUSY, "request can never fit the memory budget");
+  r->L = make_layout(*p, r->E, LAYOUT_STATE);
+  r->Lg = make_layout(*p, r->E, LAYOUT_GEOMETRY);
+  if (r->L.total + r->Lg.total > sv->budget) return fail(DG_EBUSY, "request can never fit the memory budget");
   const int ng = m->n_geo + 1, n = p->N + 1;
   r->x_geo.assign(m->x_geo, m->x_geo + (size_t)r->E * 3 * ng * ng * ng);
   r->nbr_elem.assign(m->nbr_elem, m->nbr_elem + r->E * 6);
@@ -699,8 +802,12 @@ dg_status dg_server_run(dg_server *sv, int32_t max_ticks) {
     sv->prep_cv.notify_all();  // arrival times are on the clock that starts now
   }
   int ticks = 0;
+  using clk = std::chrono::steady_clock;
+  auto secs = [](clk::time_point a) { return std::chrono::duration<double>(clk::now() - a).count(); };
   for (;;) {
+    auto c0 = clk::now();
     dg_status rc = admit(sv);
+    sv->st_admit += secs(c0);
     if (rc) return rc;
     if (sv->active.empty()) {
       double head_arrival;
@@ -711,13 +818,21 @@ dg_status dg_server_run(dg_server *sv, int32_t max_ticks) {
       }
       // nothing runs: wait for the next arrival, or for its set-up
       const double wait = std::max(head_arrival - sv->now(), 0.0005);
+      c0 = clk::now();
       std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
+      sv->st_idle += secs(c0);
       if (max_ticks > 0 && ++ticks >= max_ticks) break;
       continue;
     }
+    c0 = clk::now();
+    sv->st_active_sum += (int64_t)sv->active.size();
+    ++sv->st_ticks;
     rc = tick(sv);
+    sv->st_tick += secs(c0);
     if (rc) return rc;
+    c0 = clk::now();
     rc = retire(sv);
+    sv->st_retire += secs(c0);
     if (rc) return rc;
     if (max_ticks > 0 && ++ticks >= max_ticks) break;
   }
@@ -749,6 +864,21 @@ dg_status dg_server_fetch(dg_server *sv, int64_t req_id, double *U_host, dg_timi
   return r.state == DG_REQ_DONE ? DG_OK : fail(DG_ENONFINITE, "request failed: state not finite");
 }
 
+dg_status dg_server_stats(dg_server *sv, double out[10]) {
+  if (!sv || !out) return fail(DG_EINVAL, "NULL argument");
+  out[8] = (double)sv->st_geo_uploads;
+  out[9] = (double)sv->st_geo_hits;
+  out[0] = (double)sv->st_ticks;
+  out[1] = sv->st_ticks ? (double)sv->st_active_sum / (double)sv->st_ticks : 0.0;
+  out[2] = sv->st_admit;
+  out[3] = sv->st_tick;
+  out[4] = sv->st_retire;
+  out[5] = sv->st_gpu_wait;
+  out[6] = sv->st_idle;
+  out[7] = sv->st_upload_bytes;
+  return DG_OK;
+}
+
 void dg_server_destroy(dg_server *sv) {
   if (!sv) return;
   {
@@ -768,6 +898,7 @@ void dg_server_destroy(dg_server *sv) {
     if (sl.host) (void)hipHostFree(sl.host);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
+  if (sv->up_host) (void)hipHostFree(sv->up_host);
   for (int i = 0; i < kGroupStreams; ++i) {
     if (sv->gst[i]) {
       (void)hipStreamSynchronize(sv->gst[i]);

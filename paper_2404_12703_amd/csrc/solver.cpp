@@ -101,40 +101,42 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
-Layout make_layout(const dg_params &p, int64_t E) {
+Layout make_layout(const dg_params &p, int64_t E, int part) {
   Layout L;
   const int n = p.N + 1;
   const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n;
   const size_t rs = p.precision ? sizeof(float) : sizeof(double);
   size_t o = 0;
-  auto take = [&](size_t bytes) {
+  const bool st = part != LAYOUT_GEOMETRY, geo = part != LAYOUT_STATE;
+  auto take = [&](bool in_part, size_t bytes) {
+    if (!in_part) return SIZE_MAX;
     size_t at = o;
     o += align256(bytes);
     return at;
   };
-  L.U = take(5 * E * n3 * 8);
-  L.dU = take(5 * E * n3 * 8);
-  L.Ja = take(9 * E * n3 * rs);
-  L.invJ = take(E * n3 * rs);
-  L.NS = take(3 * E * 6 * n2 * rs);
-  L.Utr0 = take(5 * E * 6 * n2 * rs);
-  L.Utr1 = take(5 * E * 6 * n2 * rs);
+  L.U = take(st, 5 * E * n3 * 8);
+  L.dU = take(st, 5 * E * n3 * 8);
+  L.Ja = take(geo, 9 * E * n3 * rs);
+  L.invJ = take(geo, E * n3 * rs);
+  L.NS = take(geo, 3 * E * 6 * n2 * rs);
+  L.Utr0 = take(st, 5 * E * 6 * n2 * rs);
+  L.Utr1 = take(st, 5 * E * 6 * n2 * rs);
   // the two sweeps exchange each side's viscous face flux (4 values per face
   // node, viscous only) and the volume integral (5 per node)
-  L.Hv = p.viscous ? take(4 * E * 6 * n2 * rs) : SIZE_MAX;
-  L.Vol = (p.viscous || p.shock_capturing || p.volume_flux) ? take(5 * E * n3 * rs) : SIZE_MAX;
+  L.Hv = take(st && p.viscous, 4 * E * 6 * n2 * rs);
+  L.Vol = take(st && (p.viscous || p.shock_capturing || p.volume_flux), 5 * E * n3 * rs);
   // per-element dissipation sums of dg_dissipation (viscous only)
-  L.diag = p.viscous ? take(3 * E * sizeof(double)) : SIZE_MAX;
-  L.conn = take(6 * E * sizeof(int2));
-  L.Xs = p.source ? take(3 * E * n3 * 8) : SIZE_MAX;
-  L.basis = take(BasisOffsets(n).total * rs);
-  L.alpha = take(E * rs);
-  L.alpha_raw = take(E * rs);
-  L.alpha_in = take(E * rs);
+  L.diag = take(st && p.viscous, 3 * E * sizeof(double));
+  L.conn = take(geo, 6 * E * sizeof(int2));
+  L.Xs = take(geo && p.source, 3 * E * n3 * 8);
+  L.basis = take(geo, BasisOffsets(n).total * rs);
+  L.alpha = take(st, E * rs);
+  L.alpha_raw = take(st, E * rs);
+  L.alpha_in = take(st, E * rs);
   // shock capturing: the workgroups left to the blend pass (two counts,
   // used by alternate surface sweeps, and at most one entry per element)
-  L.blend = p.shock_capturing ? take((2 + E) * sizeof(int)) : SIZE_MAX;
-  L.scratch = take(kRedBlocks * 8 * sizeof(double));
+  L.blend = take(st && p.shock_capturing, (2 + E) * sizeof(int));
+  L.scratch = take(st, kRedBlocks * 8 * sizeof(double));
   L.total = o;
   return L;
 }
@@ -263,20 +265,38 @@ double host_stable_dt(const dg_params &p, int64_t E, const HostSetup &hs, const 
   return std::min(cfl * dta, cfl * dtv);
 }
 
-hipError_t setup_device(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st) {
+hipError_t upload_geometry(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st) {
   char *ws = (char *)base;
   const bool mixed = p.precision == 1;
   auto put = [&](size_t off, const std::vector<double> &d, const std::vector<float> &f) -> hipError_t {
     return mixed ? hipMemcpyAsync(ws + off, f.data(), f.size() * 4, hipMemcpyHostToDevice, st)
                  : hipMemcpyAsync(ws + off, d.data(), d.size() * 8, hipMemcpyHostToDevice, st);
   };
-  hipError_t e = hipMemsetAsync(ws, 0, L.total, st);
-  if (e == hipSuccess) e = put(L.Ja, hs.Ja, hs.fJa);
+  hipError_t e = put(L.Ja, hs.Ja, hs.fJa);
   if (e == hipSuccess) e = put(L.invJ, hs.invJ, hs.finvJ);
   if (e == hipSuccess) e = put(L.NS, hs.NS, hs.fNS);
   if (e == hipSuccess) e = put(L.basis, hs.basis, hs.fbasis);
   if (e == hipSuccess) e = hipMemcpyAsync(ws + L.conn, hs.conn.data(), hs.conn.size() * sizeof(int2), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && p.source) e = hipMemcpyAsync(ws + L.Xs, hs.Xs.data(), hs.Xs.size() * 8, hipMemcpyHostToDevice, st);
+  return e;
+}
+
+template <typename real>
+void attach_geometry(View<real> &v, void *base, const Layout &L) {
+  char *g = (char *)base;
+  v.Ja = (const real *)(g + L.Ja);
+  v.invJ = (const real *)(g + L.invJ);
+  v.NS = (const real *)(g + L.NS);
+  v.conn = (const int2 *)(g + L.conn);
+  v.Xs = L.Xs == SIZE_MAX ? nullptr : (const double *)(g + L.Xs);
+  v.basis = (const real *)(g + L.basis);
+}
+template void attach_geometry<double>(View<double> &, void *, const Layout &);
+template void attach_geometry<float>(View<float> &, void *, const Layout &);
+
+hipError_t setup_device(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(base, 0, L.total, st);
+  if (e == hipSuccess) e = upload_geometry(p, hs, base, L, st);
   return e;
 }
 

@@ -21,7 +21,12 @@ struct Layout {
       total;
 };
 
-Layout make_layout(const dg_params &p, int64_t E);
+// part 0: every array of one solve; 1: the per-solve state and temporaries
+// only; 2: the read-only geometry only (metrics, normals, connectivity, node
+// positions, operator block), which solves of one mesh can share.  Arrays of
+// the other part are SIZE_MAX.
+enum LayoutPart { LAYOUT_ALL = 0, LAYOUT_STATE = 1, LAYOUT_GEOMETRY = 2 };
+Layout make_layout(const dg_params &p, int64_t E, int part = LAYOUT_ALL);
 dg_status check_params(const dg_params *p);
 // kernels index one row of a volume or face array with 32-bit lane offsets
 inline bool elems_in_range(int N, int64_t E) {
@@ -53,9 +58,14 @@ dg_status setup_host(const dg_params &p, const dg_mesh &m, HostSetup &hs, std::s
 // in FP64 from the set-up's metrics (in the solve's arithmetic type, as on
 // the device)
 double host_stable_dt(const dg_params &p, int64_t E, const HostSetup &hs, const double *U0, double cfl);
-// zero the workspace and copy the set-up in on st; hs must stay alive until
-// the copies have completed
+// zero the workspace and copy the set-up in on st (L from LAYOUT_ALL); hs must
+// stay alive until the copies have completed
 hipError_t setup_device(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st);
+// the geometry part alone (L from LAYOUT_GEOMETRY): uploads only, no clearing
+hipError_t upload_geometry(const dg_params &p, const HostSetup &hs, void *base, const Layout &L, hipStream_t st);
+// point a view's geometry arrays at a geometry block (L from LAYOUT_GEOMETRY)
+template <typename real>
+void attach_geometry(View<real> &v, void *base, const Layout &L);
 dg_status device_error(dg_solver *s, hipError_t e, const char *what);
 
 struct ProfEvent {

@@ -232,3 +232,36 @@ def test_large_state_leaves_through_several_staging_chunks():
     assert np.array_equal(U, _alone(wl, dt))
     U2, _ = sv.fetch(rid2)
     assert np.array_equal(U2, _alone(small, _dt(small)))
+
+
+def test_resident_geometry_is_shared_and_evicted():
+    """requests of one mesh share its geometry block; under a tight budget the
+    blocks of meshes no running request uses are evicted and uploaded again
+    later; every result still equals its solve alone, bit for bit"""
+    import paper_2404_12703_amd as P
+    specs = [(3, 5), (4, 3), (3, 5), (4, 3), (2, 7), (3, 5), (2, 7), (4, 3)]
+    wls = [W.request_workload(dict(id=i, K=K, N=N, Ma=0.1 + 0.02 * i, Re=900.0, steps=3))
+           for i, (K, N) in enumerate(specs)]
+    need = max(P.workspace_bytes(w.params, w.mesh.n_elems) for w in wls)
+    # room for about two requests with their geometry: blocks must be evicted
+    sv = P.Server(arena_bytes=3 * need + (64 << 20), hbm_budget=int(2.2 * need), max_active=8)
+    ids, dts = [], []
+    for w in wls:
+        dt = _dt(w)
+        dts.append(dt)
+        ids.append(sv.submit(w.params, w.mesh, w.U0, w.steps, dt, 0.0))
+    sv.run(0)
+    st = sv.stats()
+    _say(f"[server] geometry uploads {st['geometry_uploads']:.0f}, hits {st['geometry_hits']:.0f}")
+    assert st["geometry_uploads"] + st["geometry_hits"] == len(wls)
+    assert st["geometry_uploads"] >= 3  # one per distinct mesh at least
+    for w, rid, dt in zip(wls, ids, dts):
+        U, _ = sv.fetch(rid)
+        assert np.array_equal(U, _alone(w, dt))
+    # a roomy budget: each distinct mesh is uploaded once
+    sv2 = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=8)
+    for w, dt in zip(wls, dts):
+        sv2.submit(w.params, w.mesh, w.U0, w.steps, dt, 0.0)
+    sv2.run(0)
+    st2 = sv2.stats()
+    assert st2["geometry_uploads"] == 3 and st2["geometry_hits"] == len(wls) - 3
