@@ -48,6 +48,8 @@ struct View {
   char *base;       // batched launches, in the argument view: the arena that the
                     // descriptors' pointer fields are byte offsets into
   real gamma, Rgas, rRgas, mu, lambda; // perfect gas (rRgas = 1/R); mu, lambda at T_ref under Sutherland's law
+  real bg_p, bg_H;  // mixed form: background pressure p_ref and gamma p_ref/(gamma-1) (zero in FP64)
+  double e_ref;     // mixed form: p_ref/(gamma-1), taken off the energy where the FP64 state becomes FP32
   real rTref;       // 1/T_ref (Sutherland)
   real kappa;       // lambda/mu = gamma R/((gamma - 1) Pr)
   real cpR;         // gamma R/(gamma - 1): specific total enthalpy H = cpR T + |u|^2/2

@@ -63,6 +63,14 @@ struct Pad {
   }
 };
 
+// a state value (FP64) in the arithmetic type; the mixed form's energy carries
+// the background shift (rho e - p_ref/(gamma - 1))
+template <typename real>
+__device__ __forceinline__ real to_real(double u, int c, const View<real> &v) {
+  if constexpr (sizeof(real) == 4) return (real)(c == 4 ? u - v.e_ref : u);
+  else return u;
+}
+
 // ProlongToFace of the five conservative variables at one face node from a
 // padded LDS copy of the element's state (rows of Pad<n>::size values).
 // Explicit multiply-adds in a fixed order: an element that recomputes its own
@@ -195,7 +203,7 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *view
   real *const su = sU[le < epb ? le : 0];
   if (active) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)(v.U + c * Ev)[vi];
+    for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + Pad<n>::at(i, j, k)] = to_real((v.U + c * Ev)[vi], c, v);
   }
   __syncthreads();
   if (active) {
@@ -360,6 +368,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
   const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
   const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
   const real gam = v.gamma, rR = v.rRgas;
+  const Bg<real> bg{v.bg_p, v.bg_H};
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
   if (active) {
@@ -378,8 +387,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         Um[s] = (tr + s * Ef)[im];
         Us[s] = (tr + s * Ef)[is];
       }
-      cons2prim(Um, gam, rR, Pm);
-      cons2prim(Us, gam, rR, Ps);
+      cons2prim(Um, gam, rR, Pm, bg);
+      cons2prim(Us, gam, rR, Ps, bg);
       real nsv[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -390,8 +399,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
       const real ish = real(1) / sh;
       const real nv[3] = {nsv[0] * ish, nsv[1] * ish, nsv[2] * ish};
       real Fs[5];
-      if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs);
-      else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs);
+      if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs, bg);
+      else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs, bg);
 #pragma unroll
       for (int s = 0; s < 5; ++s) sS[le][s][fn] = primary ? Fs[s] * sh : -(Fs[s] * sh);
     }
@@ -403,12 +412,12 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       Uold[c] = (v.U + c * Ev)[vi];
-      U[c] = (real)Uold[c];
+      U[c] = to_real(Uold[c], c, v);
     }
-    cons2prim(U, gam, rR, P);
-    flux_adv<0>(U, P, Fx);
-    flux_adv<1>(U, P, Fy);
-    flux_adv<2>(U, P, Fz);
+    cons2prim(U, gam, rR, P, bg);
+    flux_adv<0>(U, P, Fx, bg);
+    flux_adv<1>(U, P, Fy, bg);
+    flux_adv<2>(U, P, Fz, bg);
 #pragma unroll
     for (int c = 0; c < 9; ++c) Ja[c] = (v.Ja + c * Ev)[vi];
   }
@@ -480,7 +489,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
     // barrier of the volume integral precedes these writes)
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) sm[c * Pad<n>::size + Pad<n>::at(i, j, k)] = (real)Unew[c];
+      for (int c = 0; c < 5; ++c) sm[c * Pad<n>::size + Pad<n>::at(i, j, k)] = to_real(Unew[c], c, v);
     }
     __syncthreads();
     if (active) {
@@ -511,7 +520,8 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
 // ---------------------------------------------------------------------------
 template <int N, typename real>
 __device__ __forceinline__ void fv_subcells(real *rows, const real *sFV, bool active, int a, int i, int j, int k,
-                                            const real *P, const real *Ja, real gam, real rR, real *Vfv) {
+                                            const real *P, const real *Ja, real gam, real rR, Bg<real> bg,
+                                            real *Vfv) {
   constexpr int n = N + 1, n3 = n * n * n;
   const real *Dm = sFV;
   const real *wq = sFV + n * n;
@@ -570,9 +580,9 @@ __device__ __forceinline__ void fv_subcells(real *rows, const real *sFV, bool ac
       real UL[5], UR[5], PL[6], PR[6], F[5];
       prim2cons(qL, gam, UL);
       prim2cons(qR, gam, UR);
-      cons2prim(UL, gam, rR, PL);
-      cons2prim(UR, gam, rR, PR);
-      riemann_llf(UL, PL, UR, PR, nv, gam, F);
+      cons2prim(UL, gam, rR, PL, bg);
+      cons2prim(UR, gam, rR, PR, bg);
+      riemann_llf(UL, PL, UR, PR, nv, gam, F, bg);
 #pragma unroll
       for (int c = 0; c < 5; ++c) rows[(11 + c) * n3 + a] = F[c] * sh;
     }
@@ -701,6 +711,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
   const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
   const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
   const real gam = v.gamma, rR = v.rRgas, mu = v.mu, lam = v.lambda;
+  const Bg<real> bg{v.bg_p, v.bg_H};
   const bool visc = v.viscous != 0;  // the same for the whole grid
   constexpr bool suth = SUTH;
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
@@ -726,7 +737,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
     for (int m = 0; m < npt; ++m)
 #pragma unroll
-      for (int c = 0; c < 5; ++c) U[m][c] = (real)(v.U + c * Ev)[vi + m * tpe];
+      for (int c = 0; c < 5; ++c) U[m][c] = to_real((v.U + c * Ev)[vi + m * tpe], c, v);
   }
   if constexpr (SHOCK) {
     static_assert(npt == 1, "the indicator takes one node per thread");
@@ -735,8 +746,8 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     real eps = real(0);
     if (active) {
       real P[6];
-      cons2prim(U[0], gam, rR, P);
-      eps = P[0] * P[4];
+      cons2prim(U[0], gam, rR, P, bg);
+      eps = P[0] * full_p(P[4], bg);
     }
     const BasisOffsets o(n);
     real *r = sm + L::J;
@@ -752,7 +763,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
       for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + am] = (v.Ja + c * Ev)[vi + m * tpe];
       real P[6];
-      cons2prim(U[m], gam, rR, P);
+      cons2prim(U[m], gam, rR, P, bg);
       sm[L::V + 0 * n3 + am] = P[1];
       sm[L::V + 1 * n3 + am] = P[2];
       sm[L::V + 2 * n3 + am] = P[3];
@@ -784,8 +795,8 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
             Uo[s] = (tr + s * Ef)[io];
             Un[s] = (tr + s * Ef)[in];
           }
-          cons2prim(Uo, gam, rR, Po);
-          cons2prim(Un, gam, rR, Pn);
+          cons2prim(Uo, gam, rR, Po, bg);
+          cons2prim(Un, gam, rR, Pn, bg);
           const real vo[4] = {Po[1], Po[2], Po[3], Po[5]}, vn[4] = {Pn[1], Pn[2], Pn[3], Pn[5]};
 #pragma unroll
           for (int s = 0; s < 4; ++s) sm[L::Avg + s * nf + fn] = real(0.5) * (vo[s] + vn[s]);
@@ -1002,15 +1013,15 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     for (int m = 0; m < npt; ++m) {
       const int am = a + m * tpe;
       real P[6];
-      cons2prim(U[m], gam, rR, P);
+      cons2prim(U[m], gam, rR, P, bg);
       real Fx[5], Fy[5], Fz[5];
       if constexpr (SPLIT) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) Fx[c] = Fy[c] = Fz[c] = real(0);
       } else {
-        flux_adv<0>(U[m], P, Fx);
-        flux_adv<1>(U[m], P, Fy);
-        flux_adv<2>(U[m], P, Fz);
+        flux_adv<0>(U[m], P, Fx, bg);
+        flux_adv<1>(U[m], P, Fy, bg);
+        flux_adv<2>(U[m], P, Fz, bg);
       }
       if (visc) {
         const real lamn = suth ? mun[m] * v.kappa : lam;
@@ -1239,6 +1250,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
   const int64_t Ev = v.E * n3, Ef = v.E * 6 * n2;
   const uint32_t vi = (uint32_t)(e * n3 + a), fb = (uint32_t)(e * 6 * n2);
   const real gam = v.gamma, rR = v.rRgas;
+  const Bg<real> bg{v.bg_p, v.bg_H};
   const bool visc = v.viscous != 0;  // the same for the whole grid
   const real *tr = v.cur ? v.Utr1 : v.Utr0;
   const int i = a % n, j = (a / n) % n, k = a / n2;
@@ -1256,7 +1268,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       Uold[c] = (v.U + c * Ev)[vi];
-      su[c * Pad<n>::size + pa] = (real)Uold[c];
+      su[c * Pad<n>::size + pa] = to_real(Uold[c], c, v);
     }
   }
   if (SHOCK && le < epb && a == 0) {
@@ -1326,8 +1338,8 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         Um[s] = primary ? Uo[s] : Un[s];
         Us[s] = primary ? Un[s] : Uo[s];
       }
-      cons2prim(Um, gam, rR, Pm);
-      cons2prim(Us, gam, rR, Ps);
+      cons2prim(Um, gam, rR, Pm, bg);
+      cons2prim(Us, gam, rR, Ps, bg);
       real nsv[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -1337,8 +1349,8 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
       const real sh = sqrt(nsv[0] * nsv[0] + nsv[1] * nsv[1] + nsv[2] * nsv[2]);
       const real nv[3] = {nsv[0] / sh, nsv[1] / sh, nsv[2] / sh};
       real Fs[5];
-      if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs);
-      else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs);
+      if (v.riemann == 1) riemann_roe(Um, Pm, Us, Ps, nv, gam, Fs, bg);
+      else riemann_llf(Um, Pm, Us, Ps, nv, gam, Fs, bg);
       if (visc) {
 #pragma unroll
         for (int s = 1; s < 5; ++s) Fs[s] -= real(0.5) * ((v.Hv + (s - 1) * Ef)[im] + (v.Hv + (s - 1) * Ef)[is]);
@@ -1363,13 +1375,13 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
       real U[5], P[6], Ja[9];
       if (active) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) U[c] = (real)Uold[c];
-        cons2prim(U, gam, rR, P);
+        for (int c = 0; c < 5; ++c) U[c] = to_real(Uold[c], c, v);
+        cons2prim(U, gam, rR, P, bg);
 #pragma unroll
         for (int c = 0; c < 9; ++c) Ja[c] = (v.Ja + c * Ev)[vi];
       }
       real Vfv[5] = {0, 0, 0, 0, 0};
-      fv_subcells<N, real>(rows, sFV, active, a, i, j, k, P, Ja, gam, rR, Vfv);
+      fv_subcells<N, real>(rows, sFV, active, a, i, j, k, P, Ja, gam, rR, bg, Vfv);
       if constexpr (SPLIT) {
         // the split form's advective volume integral: two-point fluxes of
         // the primitives (rows 0-4, still those of the subcell pass), the
@@ -1384,9 +1396,9 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         // the advective DG volume integral, the three directions at once
         if (active) {
           real Fx[5], Fy[5], Fz[5];
-          flux_adv<0>(U, P, Fx);
-          flux_adv<1>(U, P, Fy);
-          flux_adv<2>(U, P, Fz);
+          flux_adv<0>(U, P, Fx, bg);
+          flux_adv<1>(U, P, Fy, bg);
+          flux_adv<2>(U, P, Fz, bg);
 #pragma unroll
           for (int ci = 0; ci < 3; ++ci)
 #pragma unroll
@@ -1477,7 +1489,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
     // (every face-phase read of the old state is behind the barrier above)
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + pa] = (real)Unew[c];
+      for (int c = 0; c < 5; ++c) su[c * Pad<n>::size + pa] = to_real(Unew[c], c, v);
     }
     __syncthreads();
     if (active) {

@@ -8,10 +8,33 @@
 
 namespace dg {
 
-// prim = (rho, u, v, w, p, T) from U = (rho, rho u, rho v, rho w, rho e);
-// rRgas = 1/R.  One reciprocal of rho replaces four divisions.
+// The background pressure p_ref the mixed form takes out of its FP32
+// arithmetic: the FP32 state carries rho e - p_ref/(gamma - 1), so ConsToPrim
+// yields p - p_ref, which the momentum fluxes use as is (a constant pressure
+// adds nothing to the discrete divergence: freestream preservation); the
+// temperature, the sound speed and the enthalpy add it back.  p = bg.p,
+// H = gamma p_ref/(gamma - 1) (the energy plus pressure of the background).
+// FP64 ignores it.
 template <typename real>
-__device__ __forceinline__ void cons2prim(const real *U, real gamma, real rRgas, real *P) {
+struct Bg {
+  real p = real(0), H = real(0);
+};
+template <typename real>
+__device__ __forceinline__ real full_p(real p, Bg<real> bg) {
+  if constexpr (sizeof(real) == 4) return p + bg.p;
+  else return p;
+}
+template <typename real>
+__device__ __forceinline__ real full_E(real E, Bg<real> bg) {  // rho e + p with the background
+  if constexpr (sizeof(real) == 4) return E + bg.H;
+  else return E;
+}
+
+// prim = (rho, u, v, w, p, T) from U = (rho, rho u, rho v, rho w, rho e);
+// rRgas = 1/R.  One reciprocal of rho replaces four divisions.  (Mixed form
+// with a background: P[4] = p - p_ref, T from p.)
+template <typename real>
+__device__ __forceinline__ void cons2prim(const real *U, real gamma, real rRgas, real *P, Bg<real> bg = {}) {
   const real rho = U[0];
   const real ir = real(1) / rho;
   const real u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
@@ -21,19 +44,19 @@ __device__ __forceinline__ void cons2prim(const real *U, real gamma, real rRgas,
   P[2] = v;
   P[3] = w;
   P[4] = p;
-  P[5] = p * (ir * rRgas);
+  P[5] = full_p(p, bg) * (ir * rRgas);
 }
 
 // advective flux in Cartesian direction d (compile-time)
 template <int d, typename real>
-__device__ __forceinline__ void flux_adv(const real *U, const real *P, real *F) {
+__device__ __forceinline__ void flux_adv(const real *U, const real *P, real *F, Bg<real> bg = {}) {
   const real ud = P[1 + d];
   F[0] = U[1 + d];
   F[1] = U[1] * ud;
   F[2] = U[2] * ud;
   F[3] = U[3] * ud;
   F[1 + d] += P[4];
-  F[4] = (U[4] + P[4]) * ud;
+  F[4] = full_E(U[4] + P[4], bg) * ud;
 }
 
 // viscous flux in direction d from primitives and lifted gradients
@@ -84,17 +107,17 @@ __device__ __forceinline__ void two_point_kep(real rL, real uL, real vL, real wL
 }
 
 template <typename real>
-__device__ __forceinline__ void flux_normal(const real *U, const real *P, const real *nv, real *F) {
+__device__ __forceinline__ void flux_normal(const real *U, const real *P, const real *nv, real *F, Bg<real> bg = {}) {
   real f[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) F[v] = real(0);
-  flux_adv<0>(U, P, f);
+  flux_adv<0>(U, P, f, bg);
 #pragma unroll
   for (int v = 0; v < 5; ++v) F[v] += f[v] * nv[0];
-  flux_adv<1>(U, P, f);
+  flux_adv<1>(U, P, f, bg);
 #pragma unroll
   for (int v = 0; v < 5; ++v) F[v] += f[v] * nv[1];
-  flux_adv<2>(U, P, f);
+  flux_adv<2>(U, P, f, bg);
 #pragma unroll
   for (int v = 0; v < 5; ++v) F[v] += f[v] * nv[2];
 }
@@ -102,11 +125,11 @@ __device__ __forceinline__ void flux_normal(const real *U, const real *P, const 
 // local Lax-Friedrichs: 1/2 (F_L + F_R).n - 1/2 max(|u.n| + c) (U_R - U_L)
 template <typename real>
 __device__ __forceinline__ void riemann_llf(const real *UL, const real *PL, const real *UR, const real *PR,
-                                            const real *nv, real gamma, real *F) {
+                                            const real *nv, real gamma, real *F, Bg<real> bg = {}) {
   real FL[5], FR[5];
-  flux_normal(UL, PL, nv, FL);
-  flux_normal(UR, PR, nv, FR);
-  const real cL = sqrt(gamma * PL[4] / PL[0]), cR = sqrt(gamma * PR[4] / PR[0]);
+  flux_normal(UL, PL, nv, FL, bg);
+  flux_normal(UR, PR, nv, FR, bg);
+  const real cL = sqrt(gamma * full_p(PL[4], bg) / PL[0]), cR = sqrt(gamma * full_p(PR[4], bg) / PR[0]);
   const real unL = PL[1] * nv[0] + PL[2] * nv[1] + PL[3] * nv[2];
   const real unR = PR[1] * nv[0] + PR[2] * nv[1] + PR[3] * nv[2];
   const real lmax = fmax(fabs(unL) + cL, fabs(unR) + cR);
@@ -119,13 +142,13 @@ __device__ __forceinline__ void riemann_llf(const real *UL, const real *PL, cons
 // Roe-averaged state.
 template <typename real>
 __device__ __forceinline__ void riemann_roe(const real *UL, const real *PL, const real *UR, const real *PR,
-                                            const real *nv, real gamma, real *F) {
+                                            const real *nv, real gamma, real *F, Bg<real> bg = {}) {
   real FL[5], FR[5];
-  flux_normal(UL, PL, nv, FL);
-  flux_normal(UR, PR, nv, FR);
+  flux_normal(UL, PL, nv, FL, bg);
+  flux_normal(UR, PR, nv, FR, bg);
   const real sL = sqrt(PL[0]), sR = sqrt(PR[0]);
   const real inv = real(1) / (sL + sR);
-  const real HL = (UL[4] + PL[4]) / PL[0], HR = (UR[4] + PR[4]) / PR[0];
+  const real HL = full_E(UL[4] + PL[4], bg) / PL[0], HR = full_E(UR[4] + PR[4], bg) / PR[0];
   real ut[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) ut[d] = (sL * PL[1 + d] + sR * PR[1 + d]) * inv;

@@ -94,6 +94,8 @@ dg_status check_params(const dg_params *p) {
   if (p->time_scheme != 0 && p->time_scheme != 1) return fail(DG_EINVAL, "time_scheme must be 0 or 1");
   if (p->alpha_smooth != 0 && p->alpha_smooth != 1) return fail(DG_EINVAL, "alpha_smooth must be 0 or 1");
   if (!std::isfinite(p->p_ref) || p->p_ref < 0.0) return fail(DG_EINVAL, "p_ref must be finite and >= 0");
+  if (p->p_ref > 0.0 && p->volume_flux == 1)
+    return fail(DG_EINVAL, "p_ref applies to the standard form (the split form's fluxes use the full pressure)");
   return DG_OK;
 }
 
@@ -172,6 +174,11 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.mu = (real)p.mu;
   v.lambda = (real)(p.gamma * p.R * p.mu / ((p.gamma - 1.0) * p.Pr));
   v.Pr = p.Pr;
+  // the mixed form's background pressure (FP64 keeps the state as it is)
+  const double pref = sizeof(real) == 4 ? p.p_ref : 0.0;
+  v.bg_p = (real)pref;
+  v.bg_H = (real)(p.gamma * pref / (p.gamma - 1.0));
+  v.e_ref = pref / (p.gamma - 1.0);
   v.rTref = (real)(p.viscosity_law ? 1.0 / p.T_ref : 1.0);
   v.kappa = (real)(p.gamma * p.R / ((p.gamma - 1.0) * p.Pr));
   v.cpR = (real)(p.gamma * p.R / (p.gamma - 1.0));
