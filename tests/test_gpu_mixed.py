@@ -54,7 +54,7 @@ def test_mixed_rhs_close_to_oracle(K, N):
 
 @pytest.mark.parametrize("K,N,Ma", [(3, 7, 0.1), (4, 5, 0.1), (3, 7, 0.05)])
 def test_mixed_rhs_with_background_shift(K, N, Ma):
-    """with p_ref = p0 (reading G21: the FP32 state carries rho e - p_ref/(gamma-1)
+    """with p_ref = p0 (the FP32 state carries rho e - p_ref/(gamma-1)
     and the momentum fluxes drop the constant p_ref, exact by freestream) the
     momentum error falls to the FP32 rounding of the flow itself; the energy
     flux still carries the background enthalpy gamma p0/(gamma-1) u, whose FP32

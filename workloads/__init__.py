@@ -296,10 +296,12 @@ def tgv_state(X, Ma, gamma, R=1.0, rho0=1.0, U0=1.0, L=1.0):
     """Taylor-Green vortex, Version II (constant temperature T0 = p0/(rho0 R))"""
     x, y, z = X[0] / L, X[1] / L, X[2] / L
     p0 = rho0 * U0 ** 2 / (gamma * Ma ** 2)
-    u = U0 * np.sin(x) * np.cos(y) * np.cos(z)
-    v = -U0 * np.cos(x) * np.sin(y) * np.cos(z)
+    sx, cx, sy, cy, cz = np.sin(x), np.cos(x), np.sin(y), np.cos(y), np.cos(z)
+    u = U0 * sx * cy * cz
+    v = -U0 * cx * sy * cz
     w = np.zeros_like(u)
-    p = p0 + rho0 * U0 ** 2 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (2.0 + np.cos(2 * z))
+    # cos 2a = cos^2 a - sin^2 a
+    p = p0 + rho0 * U0 ** 2 / 16.0 * ((cx * cx - sx * sx) + (cy * cy - sy * sy)) * (1.0 + 2.0 * cz * cz)
     rho = rho0 * p / p0
     return _cons(rho, u, v, w, p, gamma)
 
@@ -385,11 +387,12 @@ def mms_workload(K=4, N=3, steps=10, rotate=False):
 
 
 def tgv_workload(K=24, N=7, steps=100, Ma=0.1, Re=1600.0, curved=True, seed=0, precision=0,
-                 rotate=False, riemann=1, p_ref=None):
+                 rotate=False, riemann=1, p_ref=None, ngeo=None):
     """[0,2pi]^3, K^3 elements, GL nodes, Taylor-Green vortex Version II.  The
     mixed form (precision 1) takes the background pressure p0 out of its FP32
     arithmetic unless p_ref says otherwise"""
-    mesh = box_mesh(K, 0.0, 2 * np.pi, N, amp=0.05 if curved else 0.0, seed=seed, rotate=rotate)
+    mesh = box_mesh(K, 0.0, 2 * np.pi, N if ngeo is None else ngeo, amp=0.05 if curved else 0.0, seed=seed,
+                    rotate=rotate)
     if p_ref is None:
         p_ref = 1.0 / (1.4 * Ma * Ma) if precision == 1 else 0.0
     p = params(N, node_type=0, riemann=riemann, viscous=1, source=0, mu=1.0 / Re, precision=precision,
@@ -399,12 +402,13 @@ def tgv_workload(K=24, N=7, steps=100, Ma=0.1, Re=1600.0, curved=True, seed=0, p
 
 
 def compressible_tgv_workload(K=16, N=7, steps=100, Ma=1.25, Re=1600.0, curved=False, seed=0,
-                              rotate=False, alpha_max=1.0):
+                              rotate=False, alpha_max=1.0, ngeo=None):
     """the supersonic Taylor-Green vortex: [0,2pi]^3, K^3 elements, Gauss-Lobatto
     nodes, Version II at Ma = 1.25, Re = 1600, Sutherland's law with T_ref = T0 and
     Pr = 0.71, split form with Pirozzoli's flux, LLF surface flux, BR1, the modal
     indicator with FV-subcell blending, and the fourteen-stage RK scheme"""
-    mesh = box_mesh(K, 0.0, 2 * np.pi, N, amp=0.05 if curved else 0.0, seed=seed, rotate=rotate)
+    mesh = box_mesh(K, 0.0, 2 * np.pi, N if ngeo is None else ngeo, amp=0.05 if curved else 0.0, seed=seed,
+                    rotate=rotate)
     gamma, R = 1.4, 1.0
     p0 = 1.0 / (gamma * Ma ** 2)
     p = params(N, node_type=1, riemann=0, viscous=1, source=0, shock=1, gamma=gamma, R=R, Pr=0.71,
@@ -451,12 +455,18 @@ def serving_requests(n=512, seed=0, rate=1.0):
     return reqs
 
 
+_REQUEST_MESHES = {}
+
+
 def request_workload(req, precision=0):
-    """one served request: Cartesian periodic [0,2pi]^3 TGV Version II, Roe, BR1"""
+    """one served request: Cartesian periodic [0,2pi]^3 TGV Version II, Roe, BR1
+    (requests of one (K, N) share the mesh object)"""
     N, K = req["N"], req["K"]
-    mesh = box_mesh(K, 0.0, 2 * np.pi, N)
+    if (K, N) not in _REQUEST_MESHES:
+        m = box_mesh(K, 0.0, 2 * np.pi, N)
+        _REQUEST_MESHES[(K, N)] = (m, m.points(gl_points(N)))
+    mesh, X = _REQUEST_MESHES[(K, N)]
     p = params(N, node_type=0, riemann=1, viscous=1, mu=1.0 / req["Re"], precision=precision,
                p_ref=1.0 / (1.4 * req["Ma"] ** 2) if precision == 1 else 0.0)
-    X = mesh.points(gl_points(N))
     return Workload("tgv_req", p, mesh, tgv_state(X, req["Ma"], p["gamma"]), req["steps"],
                     extra=dict(Ma=req["Ma"], Re=req["Re"]))
