@@ -185,6 +185,7 @@ def solve_latency(P, wl, steps, repeats, cfl=None, dt=None):
 
 
 _STREAMS = {}
+MAX_ACTIVE = 128  # requests the server runs together (--max-active)
 
 
 def stream_workloads(W, nreq, seed, precision):
@@ -196,7 +197,7 @@ def stream_workloads(W, nreq, seed, precision):
     return _STREAMS[key]
 
 
-def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30, max_active=64):
+def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30, max_active=None):
     """the served stream: nreq seeded requests (K in 4..16, N in {3,5,7},
     Ma, Re, steps drawn per request) with Poisson arrivals at `load` times the
     measured throughput (load None: all at t = 0), FIFO admission under an
@@ -211,6 +212,8 @@ def served(P, W, nreq, seed, throughput, load=0.8, precision=0, budget=32 << 30,
         lam = load * throughput / float(np.mean(work))
         g = np.random.default_rng(seed + 1000)
         arrivals = np.cumsum(g.exponential(1.0 / lam, size=nreq))
+    if max_active is None:
+        max_active = MAX_ACTIVE
     arena = min(budget + (256 << 20), int(torch.cuda.mem_get_info()[0] * 0.8))
     sv = P.Server(arena_bytes=arena, hbm_budget=budget, max_active=max_active)
     # the whole stream is submitted before the loop starts; arrival times are
@@ -292,9 +295,14 @@ def main():
                     help="time the supersonic split-form TGV only (profiling runs of that path)")
     ap.add_argument("--only-served", action="store_true",
                     help="the served stream only (FP64, load 0.8 and all at t = 0), with the loop statistics")
+    ap.add_argument("--only-mixed", action="store_true",
+                    help="time the mixed-precision 32^3 TGV only (profiling runs of that path)")
+    ap.add_argument("--max-active", type=int, default=128, help="requests the server runs together")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
+    global MAX_ACTIVE
+    MAX_ACTIVE = args.max_active
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it", file=sys.stderr)
         sys.exit(2)
@@ -350,6 +358,17 @@ def main():
         print(json.dumps({"workload": "supersonic TGV 24^3 N=7 Lobatto, split form, 14-stage RK, FP64",
                           "steps": args.steps, "value": wc.dof * 14 * args.steps / elc, "unit": "DOF*stage/s",
                           "alpha_pos_fraction": float(np.mean(sc.alpha() > 0))}), flush=True)
+        return
+    if args.only_mixed:
+        wm = W.tgv_workload(K=32, N=7, precision=1)
+        s, dt, el, prof = time_solver(P, wm, args.steps, args.warmup, profile_pass=True)
+        vbm, sbm = algorithmic_bytes_per_dof(7, True)
+        out = {"workload": "tgv 32^3 N=7 mixed precision (p_ref = p0)", "steps": args.steps,
+               "value": wm.dof * 5 * args.steps / el, "unit": "DOF*stage/s"}
+        for key, name, b in (("lift", "k_volume", vbm), ("rhs", "k_surface", sbm)):
+            t = prof[key][0] / prof[key][1] * 1e-3
+            out[name] = {"avg_ms": t * 1e3, "alg_bytes_per_dof": b, "frac": b * wm.dof / t / 1e9 / HBM_PEAK_GBS}
+        print(json.dumps(out), flush=True)
         return
     if args.only_served:
         wl = W.tgv_workload(K=args.K, N=7, steps=10)
@@ -492,6 +511,23 @@ def main():
             "alpha_pos_fraction": float(np.mean(sc.alpha() > 0)),
             "eps_S_eps_D": [float(x) for x in sc.dissipation()], "finite": bool(np.isfinite(sc.integrals()).all())}
         del sc
+        torch.cuda.empty_cache()
+        # its evolution on 16^3 elements to t = 11 (shocks from t ~ 1.7): the
+        # quantities of the paper's compressible TGV figure, without its
+        # reference data
+        progress("supersonic TGV evolution, 16^3")
+        we = W.compressible_tgv_workload(K=16, N=7, curved=False)
+        se = P.Solver(we.params, we.mesh)
+        se.set_state(we.U0, 0.0)
+        dte = se.stable_dt(we.cfl, we.cfl)
+        evo = []
+        for blk in range(10):
+            se.advance(250, dte)
+            I, eps = se.integrals(), se.dissipation()
+            evo.append({"t": 250 * (blk + 1) * dte, "E_k": float(I[5]), "eps_S": float(eps[0]),
+                        "eps_D": float(eps[1]), "blended_fraction": float(np.mean(se.alpha() > 0))})
+        line["ctgv16_evolution"] = {"dof": we.dof, "dt": dte, "samples": evo}
+        del se
         torch.cuda.empty_cache()
         line["served"] = [served(P, W, args.serve_requests, 0, value, load=ld, precision=0)
                           for ld in (0.5, 0.8, 1.2, None)]
