@@ -434,6 +434,11 @@ def main():
                             "alg_bytes_per_launch": kd["alg_bytes_per_dof"] * wl.dof,
                             "avg_launch_ms": kd["avg_ms"]}
         line["kernels"] = kern
+        # the counter-derived fields above come from committed records, used
+        # only while the kernel sources hash to the value they were taken on
+        line["counter_records"] = {"kernel_source_hash": kernel_source_hash(),
+                                   "traffic": "profiles/traffic_tgv24_n7_fp64.json" if tr else None,
+                                   "valu_lds": "profiles/valu_tgv24_n7_fp64.json" if va else None}
         step_alg = (vol_b + surf_b) * wl.dof * 5 * args.steps / el / 1e9
         line["whole_step_alg_GBs"] = step_alg
         line["whole_step_hbm_frac"] = step_alg / HBM_PEAK_GBS
