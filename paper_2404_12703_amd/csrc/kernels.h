@@ -225,13 +225,18 @@ __global__ void __launch_bounds__(Sz<N>::threads) k_trace(const View<real> *view
 // V^-1 (x) V^-1) eps by three line transforms through LDS rows r0..r2 (V^-1
 // staged in vs), then fixed-order sums of the energies (no atomics, so the
 // value is reproducible): within each wave by lane exchanges and over the
-// waves of the element through r3..r5 where elements and waves align, else a
-// tree through r3..r5.  Every thread of the block must call it.
+// waves of the element through r3..r6 where elements and waves align, else a
+// tree through r3..r6.  The energy fractions of the top two shells (modes
+// whose largest degree is N, and N - 1) are summed directly rather than formed
+// as differences of nearly equal totals: the same quantity, but its rounding
+// is relative to itself, which in FP32 keeps the logistic's steep part from
+// amplifying the cancellation.  Every thread of the block must call it.
 // Returns the clipped logistic value on thread a == 0 of each element.
 // ---------------------------------------------------------------------------
 template <int N, typename real>
 __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *Vinv, real *r0, real *r1, real *r2,
-                                              real *r3, real *r4, real *r5, real *vs, bool active, int a, real eps) {
+                                              real *r3, real *r4, real *r5, real *r6, real *vs, bool active, int a,
+                                              real eps) {
   constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
   const int i = a % n, j = (a / n) % n, k = a / n2;
   if (active) {
@@ -253,32 +258,37 @@ __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *V
     r2[a] = t;
   }
   __syncthreads();
-  real e0 = real(0), e1 = real(0), e2 = real(0);  // energies: all modes, degrees <= N-1, <= N-2
+  // energies: all modes, largest degree <= N - 1, largest degree N, largest degree N - 1
+  real e0 = real(0), e1 = real(0), h1 = real(0), h2 = real(0);
   if (active) {
     real m = real(0);
 #pragma unroll
     for (int r = 0; r < n; ++r) m += vs[k * n + r] * r2[vnode(n, i, j, r)];
     e0 = m * m;
-    e1 = (i < N && j < N && k < N) ? e0 : real(0);
-    e2 = (i < N - 1 && j < N - 1 && k < N - 1) ? e0 : real(0);
+    const int top = max(i, max(j, k));
+    e1 = top < N ? e0 : real(0);
+    h1 = top == N ? e0 : real(0);
+    h2 = top == N - 1 ? e0 : real(0);
   }
   // each element's nodes fill whole waves (or the element is alone in the
   // workgroup): reduce within waves, then over the element's waves
   constexpr bool wave_sums = (n3 % 64 == 0) || Sz<N>::epb == 1;
-  real tot = real(0), c1 = real(0), c2 = real(0);
+  real tot = real(0), c1 = real(0), t1 = real(0), t2 = real(0);
   if constexpr (wave_sums) {
     // every lane takes part; lanes without a node add zeros
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       e0 += __shfl_xor(e0, off, 64);
       e1 += __shfl_xor(e1, off, 64);
-      e2 += __shfl_xor(e2, off, 64);
+      h1 += __shfl_xor(h1, off, 64);
+      h2 += __shfl_xor(h2, off, 64);
     }
     constexpr int W = (n3 + 63) / 64;
     if (active && (a & 63) == 0) {
       r3[a >> 6] = e0;
       r4[a >> 6] = e1;
-      r5[a >> 6] = e2;
+      r5[a >> 6] = h1;
+      r6[a >> 6] = h2;
     }
     __syncthreads();
     if (active && a == 0) {
@@ -286,14 +296,16 @@ __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *V
       for (int w = 0; w < W; ++w) {
         tot += r3[w];
         c1 += r4[w];
-        c2 += r5[w];
+        t1 += r5[w];
+        t2 += r6[w];
       }
     }
   } else {
     if (active) {
       r3[a] = e0;
       r4[a] = e1;
-      r5[a] = e2;
+      r5[a] = h1;
+      r6[a] = h2;
     }
     __syncthreads();
     constexpr int P2 = n3 <= 8 ? 8 : (n3 <= 16 ? 16 : (n3 <= 32 ? 32 : (n3 <= 64 ? 64 : (n3 <= 128 ? 128 : (n3 <= 256 ? 256 : (n3 <= 512 ? 512 : 1024))))));
@@ -303,19 +315,21 @@ __device__ __forceinline__ real indicator_raw(const View<real> &v, const real *V
         r3[a] += r3[a + st];
         r4[a] += r4[a + st];
         r5[a] += r5[a + st];
+        r6[a] += r6[a + st];
       }
       __syncthreads();
     }
     if (active && a == 0) {
       tot = r3[0];
       c1 = r4[0];
-      c2 = r5[0];
+      t1 = r5[0];
+      t2 = r6[0];
     }
   }
   real alpha = real(0);
   if (active && a == 0) {
-    const real E1 = tot > real(0) ? (tot - c1) / tot : real(0);
-    const real E2 = c1 > real(0) ? (c1 - c2) / c1 : real(0);
+    const real E1 = tot > real(0) ? t1 / tot : real(0);
+    const real E2 = c1 > real(0) ? t2 / c1 : real(0);
     const real Ev = fmax(E1, E2);
     const real T = v.ind_T;
     alpha = real(1) / (real(1) + exp(-(v.ind_s / T) * (Ev - T)));
@@ -752,7 +766,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     const BasisOffsets o(n);
     real *r = sm + L::J;
     const real al = indicator_raw<N, real>(v, v.basis + o.Vinv, r, r + n3, r + 2 * n3, r + 3 * n3, r + 4 * n3,
-                                           r + 5 * n3, r + 6 * n3, active, a, eps);
+                                           r + 5 * n3, r + 6 * n3, r + 7 * n3, active, a, eps);
     if (active && a == 0) v.alpha_raw[e] = al;
     __syncthreads();
   }
