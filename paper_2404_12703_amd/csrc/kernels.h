@@ -662,12 +662,15 @@ struct VolLds {
   // again).
   static constexpr bool plane_waves = S::n2 == 64 && S::epb == 1;
   static constexpr int npt = ((N == 7 && !SHOCK && !SPLIT) || (N == 5 && !SHOCK && !SPLIT && !f64)) ? 2 : 1;
-  static constexpr int lift_unroll = SPLIT ? 2 : ((npt == 2 && f64) ? 2 : S::n);
+  // The split form's loop also carries the two-point flux: not unrolled, it
+  // fits the register budget of two 512-thread workgroups per CU at N = 7
+  // (128 VGPRs, one spill; unrolled by 2 it needed 148, which left one
+  // workgroup per CU and took 1.04 ms instead of 0.68 ms on the 24^3
+  // supersonic TGV; 0.79 against 0.68 ms at N = 5).
+  static constexpr int lift_unroll = SPLIT ? 1 : ((npt == 2 && f64) ? 2 : S::n);
   static constexpr int tpe = n3 / npt;  // threads per element
   static constexpr int threads = npt == 1 ? S::threads : tpe;
-  // the split form holds the two-point flux's operands beside the lifting
-  // sums: registers for two 512-thread workgroups per CU
-  static constexpr int minw = npt == 1 ? (SPLIT && S::threads >= 256 ? 2 : S::minw) : 2;
+  static constexpr int minw = npt == 1 ? S::minw : 2;
   static constexpr int units = nf / fpu;
   static constexpr int upt = (units + tpe - 1) / tpe;  // units per thread
   static_assert(12 * gsz <= Ns, "g must not cover n shat");
