@@ -81,7 +81,7 @@ __device__ __forceinline__ void flux_visc(const real *P, const real *g, real mu,
 // Sec. 2.1 Eq. sutherland: the viscosity at temperature T, normalised by the
 // reference temperature: mu(T) = mu_ref 1.4042 th^(3/2) / (th + 0.4042), th = T/T_ref
 template <typename real>
-__device__ __forceinline__ real sutherland(real T, real mu_ref, real rTref) {
+__host__ __device__ __forceinline__ real sutherland(real T, real mu_ref, real rTref) {
   const real th = T * rTref;
   return mu_ref * real(1.4042) * th * sqrt(th) / (th + real(0.4042));
 }

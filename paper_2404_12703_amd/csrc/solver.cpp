@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "physics.h"
 #include "solver_impl.h"
 
 namespace dg {
@@ -265,7 +266,9 @@ double host_stable_dt(const dg_params &p, int64_t E, const HostSetup &hs, const 
       }
       dta = std::min(dta, 2.0 / ((2.0 * p.N + 1.0) * lamsum));
       if (p.viscous && p.mu > 0) {
-        const double nu = std::max(4.0 / 3.0, gam / p.Pr) * p.mu / rho;
+        // with Sutherland's law the viscosity at this node's temperature, as on the device
+        const double mu = p.viscosity_law ? sutherland<double>(pr / (rho * p.R), p.mu, 1.0 / p.T_ref) : p.mu;
+        const double nu = std::max(4.0 / 3.0, gam / p.Pr) * mu / rho;
         dtv = std::min(dtv, 4.0 / (nfac * nu * vis));
       }
     }

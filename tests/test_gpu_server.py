@@ -192,6 +192,26 @@ def test_cfl_step_and_broken_mesh():
         assert np.linalg.norm(U - ref) <= 1e-12 * np.linalg.norm(ref), req
 
 
+def test_cfl_step_with_sutherland_viscosity():
+    """the host step of a CFL request takes Sutherland's viscosity at each
+    node's temperature, as dg_stable_dt does on the device: served supersonic
+    Taylor-Green requests (split form, Sutherland, blend, fourteen stages)
+    with dt < 0 match plain solvers advanced with their own stable step"""
+    import paper_2404_12703_amd as P
+    wls = [W.compressible_tgv_workload(K=3, N=N, steps=3, curved=True, rotate=True) for N in (5, 7)]
+    _say("[server] CFL step with Sutherland's law")
+    sv = P.Server(arena_bytes=1 << 30, hbm_budget=1 << 30, max_active=4)
+    ids = [sv.submit(wl.params, wl.mesh, wl.U0, wl.steps, -0.9, 0.0) for wl in wls]
+    sv.run(0)
+    for wl, rid in zip(wls, ids):
+        assert sv.poll(rid) == P.REQ_DONE
+        U, _ = sv.fetch(rid)
+        ref = _alone(wl, _dt(wl))
+        e = np.linalg.norm(U - ref) / np.linalg.norm(ref)
+        _say(f"  N = {wl.params['N']}: served vs alone {e:.2e}")
+        assert e <= 1e-12
+
+
 def _rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
