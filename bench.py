@@ -159,7 +159,8 @@ def time_solver(P, wl, steps, warmup, profile_pass=True):
 
 def solve_latency(P, wl, steps, repeats, cfl=None, dt=None):
     """`repeats` full solves (set_state from a device copy, `steps` RK steps,
-    state read back into device memory), each timed on the host clock.
+    state read back into device memory), each timed on the host clock, after
+    one untimed solve (the first launch of each kernel loads its code object).
     Returns p50/p99 and the solver, holding the last solve's final state."""
     import torch
     s = P.Solver(wl.params, wl.mesh)
@@ -170,14 +171,15 @@ def solve_latency(P, wl, steps, repeats, cfl=None, dt=None):
     U0 = torch.from_numpy(wl.U0).cuda()
     out = torch.empty_like(U0)
     lat = []
-    for _ in range(repeats):
+    for rep in range(repeats + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.set_state(U0, 0.0)
         s.advance(steps, dt)
         s.state_into(out)
         s.synchronize()
-        lat.append(time.perf_counter() - t0)
+        if rep:
+            lat.append(time.perf_counter() - t0)
     st = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)), "repeats": repeats,
           "steps": steps, "dt": dt, "solve": f"set_state + {steps} steps + get_state",
           "value_at_p50": wl.dof * 5 * steps / float(np.percentile(lat, 50))}
