@@ -53,6 +53,7 @@ struct View {
   real rTref;       // 1/T_ref (Sutherland)
   real kappa;       // lambda/mu = gamma R/((gamma - 1) Pr)
   real cpR;         // gamma R/(gamma - 1): specific total enthalpy H = cpR T + |u|^2/2
+  real Rgas4, cpR2; // 4 R and 2 cpR (the split form's two-point sums)
   double Pr;        // Prandtl number (time-step estimate only)
   double t, dt, rkA, rkB;       // stage time, step, LSERK coefficients
   int cur;          // trace buffer read this stage (0: Utr0, 1: Utr1)

@@ -711,11 +711,14 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
   const View<real> v = select_view(views, blk_start, nreq, single, lblk);
   __shared__ Smem<N, real> sb;
   __shared__ __align__(16) real sA[epb][L::rows];
-  __shared__ real sDs[SPLIT ? n * (n + 1) : 1];  // D + D-hat, rows padded to n + 1
+  // (D + D-hat)/16, rows padded to n + 1: the weights of the two-point sums
+  // (two_point_kep_sums), exact scaling by a power of two
+  __shared__ real sDs[SPLIT ? n * (n + 1) : 1];
   load_basis<N, real>(sb, v.basis);
   if constexpr (SPLIT) {
     const BasisOffsets o(n);
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) sDs[(t / n) * (n + 1) + t % n] = v.basis[o.D + t] + v.basis[o.Dhat + t];
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x)
+      sDs[(t / n) * (n + 1) + t % n] = (v.basis[o.D + t] + v.basis[o.Dhat + t]) * real(0.0625);
   }
   // thread a of an element holds its nodes a + m tpe, m < npt: the same i and
   // j, and k = k0 + m kstep
@@ -847,10 +850,10 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     for (int m = 0; m < npt; ++m)
 #pragma unroll
       for (int c = 0; c < 12; ++c) JG[m][c] = real(0);
-    // own operands of the two-point flux (split form)
-    real orho[npt], ou[npt], ov[npt], ow[npt], op[npt], oH[npt];
+    // own operands of the two-point flux (split form): rho, u, v, w, 4 p and 2 H
+    real orho[npt], ou[npt], ov[npt], ow[npt], op4[npt], oH2[npt];
+    const real R4 = v.Rgas4, cp2R = v.cpR2;
     if constexpr (SPLIT) {
-      const real Rg = v.Rgas, cpR = v.cpR;
 #pragma unroll
       for (int m = 0; m < npt; ++m) {
         const int am = a + m * tpe;
@@ -859,8 +862,8 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
         ov[m] = sm[L::V + n3 + am];
         ow[m] = sm[L::V + 2 * n3 + am];
         const real T = sm[L::V + 3 * n3 + am];
-        op[m] = orho[m] * (Rg * T);
-        oH[m] = cpR * T + real(0.5) * (ou[m] * ou[m] + ov[m] * ov[m] + ow[m] * ow[m]);
+        op4[m] = orho[m] * (R4 * T);
+        oH2[m] = cp2R * T + (ou[m] * ou[m] + ov[m] * ov[m] + ow[m] * ow[m]);
       }
     }
 #pragma unroll
@@ -918,15 +921,14 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
         }
         if constexpr (SPLIT) {
           const real rs = sm[L::Rho + src];
-          const real ps = rs * (v.Rgas * vv[3]);
-          const real Hs = v.cpR * vv[3] + real(0.5) * (vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
-          real F[5];
-          two_point_kep(orho[m], ou[m], ov[m], ow[m], op[m], oH[m], rs, vv[0], vv[1], vv[2], ps, Hs,
-                        real(0.5) * (oJ[m][0] + jr[0]), real(0.5) * (oJ[m][1] + jr[1]),
-                        real(0.5) * (oJ[m][2] + jr[2]), F);
-          const real ds = sDs[idx * (n + 1) + al];
+          const real ps4 = rs * (R4 * vv[3]);
+          const real Hs2 = cp2R * vv[3] + (vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+          real G[5];
+          two_point_kep_sums(orho[m] + rs, ou[m] + vv[0], ov[m] + vv[1], ow[m] + vv[2], op4[m] + ps4, oH2[m] + Hs2,
+                             oJ[m][0] + jr[0], oJ[m][1] + jr[1], oJ[m][2] + jr[2], G);
+          const real ds = sDs[idx * (n + 1) + al];  // (D + D-hat)/16
 #pragma unroll
-          for (int c = 0; c < 5; ++c) Vs[m][c] += ds * F[c];
+          for (int c = 0; c < 5; ++c) Vs[m][c] += ds * G[c];
         }
       };
 #pragma unroll L::lift_unroll
@@ -1194,6 +1196,14 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
             }
           }
         }
+      }
+    }
+    if constexpr (SPLIT) {
+      // the two-point sums carry 8 F_0, 16 F_1..3 and 32 F_4 against weights /16
+#pragma unroll
+      for (int m = 0; m < npt; ++m) {
+        Vs[m][0] *= real(2);
+        Vs[m][4] *= real(0.5);
       }
     }
 #pragma unroll

@@ -106,6 +106,22 @@ __device__ __forceinline__ void two_point_kep(real rL, real uL, real vL, real wL
   F[4] = mf * H;
 }
 
+// The same flux from sums instead of means, for the volume sweep's inner
+// loop: with S_x = x_L + x_R, S_p4 = 4 (p_L + p_R), S_H2 = 2 (H_L + H_R) and
+// s = Ja_L + Ja_R it returns G = (8 F_0, 16 F_1, 16 F_2, 16 F_3, 32 F_4).  Each
+// halving of the means is a power of two, so G is F scaled exactly; the
+// caller folds the factors into its weights.
+template <typename real>
+__device__ __forceinline__ void two_point_kep_sums(real Sr, real Su, real Sv, real Sw, real Sp4, real SH2, real s0,
+                                                   real s1, real s2, real *G) {
+  const real X = Sr * (Su * s0 + Sv * s1 + Sw * s2);
+  G[0] = X;
+  G[1] = X * Su + Sp4 * s0;
+  G[2] = X * Sv + Sp4 * s1;
+  G[3] = X * Sw + Sp4 * s2;
+  G[4] = X * SH2;
+}
+
 template <typename real>
 __device__ __forceinline__ void flux_normal(const real *U, const real *P, const real *nv, real *F, Bg<real> bg = {}) {
   real f[5];

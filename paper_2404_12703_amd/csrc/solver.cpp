@@ -183,6 +183,8 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
   v.rTref = (real)(p.viscosity_law ? 1.0 / p.T_ref : 1.0);
   v.kappa = (real)(p.gamma * p.R / ((p.gamma - 1.0) * p.Pr));
   v.cpR = (real)(p.gamma * p.R / (p.gamma - 1.0));
+  v.Rgas4 = real(4) * (real)p.R;
+  v.cpR2 = real(2) * v.cpR;
   v.split = p.volume_flux;
   v.visc_law = p.viscosity_law;
   v.alpha_smooth = p.alpha_smooth;
