@@ -1156,11 +1156,14 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
   // VolInt: the fluxes of all three directions at once (split form: the
   // viscous fluxes; without viscosity there is nothing left to contract)
   const bool contract = !SPLIT || visc;
+  // the viscous fluxes have no mass component: the split form contracts four
+  constexpr int c0 = SPLIT ? 1 : 0;
   if (active && contract) {
 #pragma unroll
     for (int m = 0; m < npt; ++m)
 #pragma unroll
-      for (int c = 0; c < 15; ++c) sm[L::F + c * n3 + a + m * tpe] = Fc[m][c];
+      for (int c = 0; c < 15; ++c)
+        if (c % 5 >= c0) sm[L::F + c * n3 + a + m * tpe] = Fc[m][c];
   }
   __syncthreads();
   if (active) {
@@ -1181,18 +1184,18 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
               const int km = k0 + m * kstep;
               const int src = ci == 0 ? vnode(n, alp, j, km) : vnode(n, i, alp, km);
 #pragma unroll
-              for (int c = 0; c < 5; ++c) Vi[m][c] += dh * sm[L::F + (5 * ci + c) * n3 + src];
+              for (int c = c0; c < 5; ++c) Vi[m][c] += dh * sm[L::F + (5 * ci + c) * n3 + src];
             }
           } else {
             const int src = vnode(n, i, j, alp);
             real fz[5];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) fz[c] = sm[L::F + (10 + c) * n3 + src];
+            for (int c = c0; c < 5; ++c) fz[c] = sm[L::F + (10 + c) * n3 + src];
 #pragma unroll
             for (int m = 0; m < npt; ++m) {
               const real dh = plane_waves ? dk[m][alp] : sb.Dh[(k0 + m * kstep) * (n + 1) + alp];
 #pragma unroll
-              for (int c = 0; c < 5; ++c) Vi[m][c] += dh * fz[c];
+              for (int c = c0; c < 5; ++c) Vi[m][c] += dh * fz[c];
             }
           }
         }
