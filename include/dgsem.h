@@ -77,7 +77,8 @@ typedef struct dg_params {
   int32_t check_finite;    /* 1: dg_advance checks the state after every step and reports the first non-finite one */
   int32_t reserved;
   double gamma, R, Pr, mu; /* mu: the constant viscosity, or mu(T_ref) under Sutherland's law */
-  double alpha_max, alpha_min; /* blending clip: alpha < alpha_min -> 0, > 1-alpha_min -> 1, then min(alpha, alpha_max) */
+  double alpha_max, alpha_min; /* blending clip: alpha < alpha_min -> 0, > 1-alpha_min -> 1, then min(alpha, alpha_max);
+                                  0 <= alpha_min < 1/2, 0 <= alpha_max <= 1 */
   double ind_a, ind_c, ind_s;  /* threshold T = ind_a 10^(-ind_c (N+1)^(1/4)); alpha = 1/(1+exp(-ind_s/T (E-T))) */
   /* ---- since ABI version 2 ---- */
   int32_t volume_flux;     /* 0 standard weak-form volume integral (Eq. dgsem);
@@ -250,8 +251,9 @@ dg_status dg_server_create(void *d_arena, size_t arena_bytes, size_t hbm_budget,
 /* Queue one solve: parameters, mesh, initial state (host [5][E][(N+1)^3]),
  * n_steps of size dt.  dt < 0 asks for the stable step of dg_stable_dt with
  * CFL = DFL = -dt on the initial state, evaluated in FP64 on the host when
- * the request is prepared.  All host data is copied.  t_arrival: seconds on
- * the server clock, which starts at the first dg_server_run call (so a
+ * the request is prepared.  All host data is copied.  t_arrival: finite
+ * seconds >= 0 on the server clock, which starts at the first dg_server_run
+ * call (so a
  * stream can be submitted up front); the request becomes eligible for
  * admission once the server clock passes it.  Once a request has arrived, a
  * thread of the server builds its geometry and metrics while the serving loop

@@ -763,6 +763,7 @@ dg_status dg_server_submit(dg_server *sv, const dg_params *p, const dg_mesh *m, 
   if (!elems_in_range(p->N, m->n_elems) || m->n_geo < 1 || m->n_geo > p->N)
     return fail(DG_EINVAL, "bad mesh sizes");
   if (n_steps < 0 || !std::isfinite(dt) || dt == 0.0) return fail(DG_EINVAL, "need n_steps >= 0 and dt != 0");
+  if (!std::isfinite(t_arrival) || t_arrival < 0.0) return fail(DG_EINVAL, "t_arrival must be finite and >= 0");
   std::unique_ptr<Request> r(new Request());
   r->id = sv->next_id++;
   r->p = *p;

@@ -83,15 +83,19 @@ dg_status check_params(const dg_params *p) {
   if (p->precision != 0 && p->precision != 1) return fail(DG_EINVAL, "precision must be 0 or 1");
   if (p->shock_capturing && (p->nodes != 1 || p->N < 2 || p->N > 7))
     return fail(DG_EINVAL, "shock capturing needs Gauss-Lobatto nodes and 2 <= N <= 7");
-  if (!(p->gamma > 1.0) || !(p->R > 0.0) || !(p->Pr > 0.0) || !(p->mu >= 0.0))
-    return fail(DG_EINVAL, "need gamma > 1, R > 0, Pr > 0, mu >= 0");
-  if (p->shock_capturing && !(p->alpha_max >= 0.0 && p->alpha_max <= 1.0 && p->alpha_min >= 0.0 && p->ind_a > 0.0))
-    return fail(DG_EINVAL, "bad indicator parameters");
+  if (!(p->gamma > 1.0) || !(p->R > 0.0) || !(p->Pr > 0.0) || !(p->mu >= 0.0) || !std::isfinite(p->gamma) ||
+      !std::isfinite(p->R) || !std::isfinite(p->Pr) || !std::isfinite(p->mu))
+    return fail(DG_EINVAL, "need finite gamma > 1, R > 0, Pr > 0, mu >= 0");
+  if (p->shock_capturing &&
+      !(p->alpha_max >= 0.0 && p->alpha_max <= 1.0 && p->alpha_min >= 0.0 && p->alpha_min < 0.5 && p->ind_a > 0.0 &&
+        std::isfinite(p->ind_a) && std::isfinite(p->ind_c) && p->ind_s > 0.0 && std::isfinite(p->ind_s)))
+    return fail(DG_EINVAL, "bad indicator parameters (need 0 <= alpha_min < 0.5, 0 <= alpha_max <= 1, finite a, c and s, "
+                           "a > 0, s > 0)");
   if (p->volume_flux != 0 && p->volume_flux != 1) return fail(DG_EINVAL, "volume_flux must be 0 or 1");
   if (p->volume_flux == 1 && p->nodes != 1) return fail(DG_EINVAL, "the split form needs Gauss-Lobatto nodes");
   if (p->viscosity_law != 0 && p->viscosity_law != 1) return fail(DG_EINVAL, "viscosity_law must be 0 or 1");
-  if (p->viscosity_law == 1 && !(p->T_ref > 0.0 && p->mu > 0.0))
-    return fail(DG_EINVAL, "Sutherland's law needs T_ref > 0 and mu > 0");
+  if (p->viscosity_law == 1 && !(p->T_ref > 0.0 && std::isfinite(p->T_ref) && p->mu > 0.0))
+    return fail(DG_EINVAL, "Sutherland's law needs a finite T_ref > 0 and mu > 0");
   if (p->time_scheme != 0 && p->time_scheme != 1) return fail(DG_EINVAL, "time_scheme must be 0 or 1");
   if (p->alpha_smooth != 0 && p->alpha_smooth != 1) return fail(DG_EINVAL, "alpha_smooth must be 0 or 1");
   if (!std::isfinite(p->p_ref) || p->p_ref < 0.0) return fail(DG_EINVAL, "p_ref must be finite and >= 0");
@@ -541,6 +545,7 @@ void dg_destroy(dg_solver *s) {
 dg_status dg_set_state(dg_solver *s, const double *U, int32_t on_device, double t) {
   CHECK_SOLVER(s);
   if (!U) return fail(DG_EINVAL, "U is NULL");
+  if (!std::isfinite(t)) return fail(DG_EINVAL, "t must be finite");
   size_t bytes = (size_t)5 * s->E * (s->p.N + 1) * (s->p.N + 1) * (s->p.N + 1) * 8;
   hipError_t e = hipMemcpyAsync((char *)s->ws + s->L.U, U, bytes,
                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->st);
@@ -592,6 +597,7 @@ dg_status dg_advance(dg_solver *s, int32_t n_steps, double dt) {
 dg_status dg_rhs(dg_solver *s, double t, double *Ut, int32_t on_device) {
   CHECK_SOLVER(s);
   if (!Ut) return fail(DG_EINVAL, "Ut is NULL");
+  if (!std::isfinite(t)) return fail(DG_EINVAL, "t must be finite");
   // a host destination is staged through the RK register, which carries no
   // information between steps (A_1 = 0 restarts it)
   double *dst = on_device ? Ut : (double *)((char *)s->ws + s->L.dU);
@@ -607,7 +613,8 @@ dg_status dg_rhs(dg_solver *s, double t, double *Ut, int32_t on_device) {
 
 dg_status dg_stable_dt(dg_solver *s, double cfl, double dfl, double *dt) {
   CHECK_SOLVER(s);
-  if (!dt || !(cfl > 0) || !(dfl > 0)) return fail(DG_EINVAL, "bad arguments");
+  if (!dt || !(cfl > 0) || !(dfl > 0) || !std::isfinite(cfl) || !std::isfinite(dfl))
+    return fail(DG_EINVAL, "need dt and finite cfl, dfl > 0");
   double *scr = (double *)((char *)s->ws + s->L.scratch);
   hipError_t e = s->mixed ? launch_dt<float>(s->p.N, s->vf, scr, kRedBlocks, s->st)
                           : launch_dt<double>(s->p.N, s->vd, scr, kRedBlocks, s->st);

@@ -64,8 +64,13 @@ def test_workspace_bytes_and_parameter_checks():
     with pytest.raises(b.DGError) as ei:
         b.workspace_bytes(p, (2**31 - 1) // n3 + 1)
     assert ei.value.code == b.DG_EINVAL
+    inf, nan = float("inf"), float("nan")
+    lob = dict(nodes=1, shock_capturing=1)
     for bad in (dict(N=0), dict(N=12), dict(gamma=1.0), dict(Pr=0.0), dict(mu=-1.0), dict(riemann=3),
-                dict(nodes=0, shock_capturing=1)):
+                dict(nodes=0, shock_capturing=1), dict(gamma=inf), dict(R=nan), dict(Pr=inf), dict(mu=inf),
+                dict(lob, ind_s=0.0), dict(lob, ind_s=nan), dict(lob, ind_c=inf), dict(lob, ind_a=inf),
+                dict(lob, alpha_min=0.5), dict(lob, alpha_max=1.5), dict(viscosity=1, T_ref=inf),
+                dict(p_ref=nan)):
         q = dict(p)
         q.update(bad)
         with pytest.raises(b.DGError) as ei:
