@@ -671,10 +671,10 @@ struct VolLds {
   static constexpr int tpe = n3 / npt;  // threads per element
   static constexpr int threads = npt == 1 ? S::threads : tpe;
   static constexpr int minw = npt == 1 ? S::minw : 2;
-  // FP64 column pairs at N = 7: the xi and eta contractions of the volume
-  // integral on the matrix cores (4x4x4, four blocks), results in the lanes
-  // that own them (see k_volume)
-  static constexpr bool mfma = npt == 2 && f64 && N == 7;
+  // FP64 at N = 7 (a wave is one k-plane): the xi and eta contractions of the
+  // volume integral on the matrix cores (4x4x4, four blocks), results in the
+  // lanes that own them (see k_volume)
+  static constexpr bool mfma = f64 && N == 7;
   static constexpr int units = nf / fpu;
   static constexpr int upt = (units + tpe - 1) / tpe;  // units per thread
   static_assert(12 * gsz <= Ns, "g must not cover n shat");
@@ -1179,8 +1179,9 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     if (contract && L::mfma) {
       // xi and eta on the FP64 4x4x4 four-block matrix instruction.  Its
       // operands sit at A[m][k]: lane 16k + 4b + m, B[k][n]: lane 16k + 4b + n,
-      // and its result at D[m][n]: lane 16m + 4b + n.  A wave is one k-plane
-      // pair with node (i, j) on lane i + 8j, so taking i = n + 4 (b & 1) and
+      // and its result at D[m][n]: lane 16m + 4b + n.  A wave holds one
+      // k-plane (with column pairs also the plane n/2 above) with node (i, j)
+      // on lane i + 8j, so taking i = n + 4 (b & 1) and
       // j = (b >> 1) + 2m as the output indices puts every result in the lane
       // that owns the node.  xi: A = fluxes (row j, source l), B = D-hat^T;
       // eta: A = D-hat (row j), B = fluxes (column i, source l); sources in
@@ -1197,7 +1198,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
       for (int m = 0; m < npt; ++m) {
         const int km = k0 + m * kstep;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
+        for (int c = c0; c < 5; ++c) {
           double acc = 0.0;
 #pragma unroll
           for (int h = 0; h < 2; ++h)
@@ -1216,12 +1217,12 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
         const int src = vnode(n, i, j, alp);
         real fz[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) fz[c] = sm[L::F + (10 + c) * n3 + src];
+        for (int c = c0; c < 5; ++c) fz[c] = sm[L::F + (10 + c) * n3 + src];
 #pragma unroll
         for (int m = 0; m < npt; ++m) {
           const real dh = plane_waves ? dk[m][alp] : sb.Dh[(k0 + m * kstep) * (n + 1) + alp];
 #pragma unroll
-          for (int c = 0; c < 5; ++c) Vi[m][c] += dh * fz[c];
+          for (int c = c0; c < 5; ++c) Vi[m][c] += dh * fz[c];
         }
       }
     } else if (contract) {
