@@ -106,9 +106,13 @@ def pid_sweep(P, W, Ks, steps, split):
     return rows
 
 
+_T0 = time.perf_counter()
+
+
 def progress(msg):
-    """a progress line on stderr (stdout carries the one JSON result line)"""
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    """a progress line on stderr (stdout carries the one JSON result line),
+    with the seconds since the start"""
+    print(f"[bench {time.perf_counter() - _T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -300,6 +304,9 @@ def main():
     ap.add_argument("--only-mixed", action="store_true",
                     help="time the mixed-precision 32^3 TGV only (profiling runs of that path)")
     ap.add_argument("--max-active", type=int, default=128, help="requests the server runs together")
+    ap.add_argument("--full", action="store_true",
+                    help="every section at full size (about 7 minutes): the served stream at four FP64 loads "
+                         "and two mixed, the PID sweep to 1e8 DOF, five solves per mixed-precision latency")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -449,11 +456,12 @@ def main():
     if not args.no_extras and not args.only_main:
         # mixed precision against FP64 on the 32^3 mesh: 500 steps with the same dt,
         # five full solves each; E_k and the state of the last solves compared
-        progress("mixed precision against FP64, 32^3, 500 steps x 5 solves each")
+        nmix = 5 if args.full else 3
+        progress(f"mixed precision against FP64, 32^3, 500 steps x {nmix} solves each")
         wd = W.tgv_workload(K=32, N=7, precision=0)
         wm = W.tgv_workload(K=32, N=7, precision=1)
-        std, sd, Ud = solve_latency(P, wd, 500, 5)
-        stm, sm, Um = solve_latency(P, wm, 500, 5, dt=std["dt"])
+        std, sd, Ud = solve_latency(P, wd, 500, nmix)
+        stm, sm, Um = solve_latency(P, wm, 500, nmix, dt=std["dt"])
         Id, Im = sd.integrals(), sm.integrals()
         # per-kernel times of the mixed form (HIP events on its stream)
         sm.profile(True)
@@ -536,13 +544,19 @@ def main():
         line["ctgv16_evolution"] = {"dof": we.dof, "dt": dte, "samples": evo}
         del se
         torch.cuda.empty_cache()
-        line["served"] = [served(P, W, args.serve_requests, 0, value, load=ld, precision=0)
-                          for ld in (0.5, 0.8, 1.2, None)]
-        line["served"] += [served(P, W, args.serve_requests, 0, value, load=ld, precision=1) for ld in (0.8, None)]
+        # the served stream: at the arrival ceiling (load 0.8) and saturated
+        # (all at t = 0); --full adds loads 0.5 and 1.2 in FP64 and 0.8 mixed
+        loads64 = (0.5, 0.8, 1.2, None) if args.full else (0.8, None)
+        loads32 = (0.8, None) if args.full else (None,)
+        line["served"] = [served(P, W, args.serve_requests, 0, value, load=ld, precision=0) for ld in loads64]
+        line["served"] += [served(P, W, args.serve_requests, 0, value, load=ld, precision=1) for ld in loads32]
         progress("PID sweep")
-        line["pid_sweep_n7"] = {
-            "standard_gauss": pid_sweep(P, W, (3, 4, 6, 8, 12, 16, 24, 32, 48, 58), 20, split=False),
-            "split_lobatto": pid_sweep(P, W, (3, 4, 6, 8, 12, 16, 24, 32, 48), 20, split=True)}
+        # to 1.7e7 DOF by default (the PID is flat above 1e6); --full to 1e8
+        ks = (3, 4, 6, 8, 12, 16, 24, 32, 48, 58) if args.full else (3, 4, 6, 8, 12, 16, 24, 32)
+        kss = (3, 4, 6, 8, 12, 16, 24, 32, 48) if args.full else (3, 6, 12, 24)
+        line["pid_sweep_n7"] = {"standard_gauss": pid_sweep(P, W, ks, 20, split=False),
+                                "split_lobatto": pid_sweep(P, W, kss, 20, split=True)}
+        line["bench_sections"] = "full" if args.full else "default (bench.py --full for every load and size)"
         line["memory_per_dof"] = memory_per_dof(P, W)
     if not args.no_cpu and not args.only_main:
         progress("CPU oracle baseline")
