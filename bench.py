@@ -442,6 +442,14 @@ def main():
                             "traffic": kd["traffic_bytes_per_launch"],
                             "alg_bytes_per_launch": kd["alg_bytes_per_dof"] * wl.dof,
                             "avg_launch_ms": kd["avg_ms"]}
+        if va and kd.get("lds_idx_active") is not None:
+            # what holds the dominant kernel below the HBM roofline, from the
+            # committed SQ counter record of the same kernel sources
+            lim = (f"LDS: its index unit is active in {kd['lds_idx_active']:.2f} of the CU-busy cycles while FP64 "
+                   f"arithmetic runs at {kd['fp64_frac']:.2f} of peak")
+            if kd["traffic_bytes_per_launch"]:
+                lim += f" and measured HBM traffic at {kd['traffic_bytes_per_launch'] / (kd['avg_ms'] * 1e6):.0f} GB/s"
+            line["roofline"]["limiter"] = lim
         line["kernels"] = kern
         # the counter-derived fields above come from committed records, used
         # only while the kernel sources hash to the value they were taken on
