@@ -313,7 +313,7 @@ def main():
     global MAX_ACTIVE
     MAX_ACTIVE = args.max_active
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it", file=sys.stderr)
+        print("bench.py: measures one GPU (--gpus 1); the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
