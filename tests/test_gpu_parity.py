@@ -233,6 +233,32 @@ def test_error_paths():
     assert ei.value.code == -5
 
 
+def test_non_finite_arguments_are_rejected():
+    """times, steps and CFL numbers that are not finite are refused before any
+    work is queued, and the solver and server stay usable"""
+    import paper_2404_12703_amd as P
+    wl = W.mms_workload(K=2, N=3)
+    s = _solver(wl.params, wl.mesh)
+    nan, inf = float("nan"), float("inf")
+    for call in (lambda: s.set_state(wl.U0, nan), lambda: s.rhs(inf), lambda: s.advance(1, nan),
+                 lambda: s.advance(1, inf), lambda: s.stable_dt(inf, 0.9), lambda: s.stable_dt(0.9, nan)):
+        with pytest.raises(P.DGError) as ei:
+            call()
+        assert ei.value.code == -1
+    s.set_state(wl.U0, 0.0)
+    dt = s.stable_dt(0.9, 0.9)
+    s.advance(1, dt)
+    assert np.isfinite(s.state()).all()
+    sv = P.Server(arena_bytes=1 << 28, hbm_budget=1 << 28, max_active=2)
+    for t_arr in (inf, nan, -1.0):
+        with pytest.raises(P.DGError) as ei:
+            sv.submit(wl.params, wl.mesh, wl.U0, 2, dt, t_arr)
+        assert ei.value.code == -1
+    rid = sv.submit(wl.params, wl.mesh, wl.U0, 2, dt, 0.0)
+    sv.run(0)
+    assert sv.poll(rid) == P.REQ_DONE
+
+
 def test_nonfinite_step_reported_and_recovery():
     """check_finite names the first non-finite step and stops there; a good
     state loaded afterwards steps exactly as a fresh solve (the RK register is
