@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
     real U[5], P[6];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      Uold[c] = (v.U + c * Ev)[vi];
+      Uold[c] = __builtin_nontemporal_load(v.U + c * Ev + vi);
       U[c] = to_real(Uold[c], c, v);
     }
     cons2prim(U, gam, rR, P, bg);
@@ -491,10 +491,10 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         double *dUc = v.dU + c * Ev;
         // the first stage (A = 0) does not read the register: whatever it
         // holds (a restored state, an aborted step) cannot leak into the step
-        const double du = (v.rkA != 0.0 ? v.rkA * dUc[vi] : 0.0) + v.dt * R[c];
-        dUc[vi] = du;
+        const double du = (v.rkA != 0.0 ? v.rkA * __builtin_nontemporal_load(dUc + vi) : 0.0) + v.dt * R[c];
+        __builtin_nontemporal_store(du, dUc + vi);
         Unew[c] = Uold[c] + v.rkB * du;
-        (v.U + c * Ev)[vi] = Unew[c];
+        __builtin_nontemporal_store(Unew[c], v.U + c * Ev + vi);
       }
     }
   }
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         real t[5];
         prolong_state<n>(sm, (f & 1) ? sb.lp : sb.lm, base, stride, t);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
+        for (int c = 0; c < 5; ++c) __builtin_nontemporal_store(t[c], trn + c * Ef + fb + fn);
       }
     }
   }
@@ -761,7 +761,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
     for (int m = 0; m < npt; ++m)
 #pragma unroll
-      for (int c = 0; c < 5; ++c) U[m][c] = to_real((v.U + c * Ev)[vi + m * tpe], c, v);
+      for (int c = 0; c < 5; ++c) U[m][c] = to_real(__builtin_nontemporal_load(v.U + c * Ev + vi + m * tpe), c, v);
   }
   // Lift_FillFlux operands: both sides' U traces and this side's n shat at
   // the thread's face nodes.  With one node per thread they are fetched here,
@@ -816,7 +816,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     for (int m = 0; m < npt; ++m) {
       const int am = a + m * tpe;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + am] = (v.Ja + c * Ev)[vi + m * tpe];
+      for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + am] = __builtin_nontemporal_load(v.Ja + c * Ev + vi + m * tpe);
       real P[6];
       cons2prim(U[m], gam, rR, P, bg);
       sm[L::V + 0 * n3 + am] = P[1];
@@ -1173,7 +1173,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
           for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[2];
 #pragma unroll
-          for (int s = 1; s < 5; ++s) (v.Hv + (s - 1) * Ef)[fb + fn] = H[s];
+          for (int s = 1; s < 5; ++s) __builtin_nontemporal_store(H[s], v.Hv + (s - 1) * Ef + fb + fn);
         }
       }
     }
@@ -1287,7 +1287,8 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
     for (int m = 0; m < npt; ++m)
 #pragma unroll
-      for (int c = 0; c < 5; ++c) (v.Vol + c * Ev)[vi + m * tpe] = SPLIT ? Vs[m][c] + Vi[m][c] : Vi[m][c];
+      for (int c = 0; c < 5; ++c)
+        __builtin_nontemporal_store(SPLIT ? Vs[m][c] + Vi[m][c] : Vi[m][c], v.Vol + c * Ev + vi + m * tpe);
   }
   if constexpr (DIAG) {
     // the element's dissipation sums in a fixed order (reproducible, no atomics)
@@ -1372,7 +1373,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
   if (active) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      Uold[c] = (v.U + c * Ev)[vi];
+      Uold[c] = __builtin_nontemporal_load(v.U + c * Ev + vi);
       su[c * Pad<n>::size + pa] = to_real(Uold[c], c, v);
     }
   }
@@ -1547,7 +1548,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
   if (active) {
     real V[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) V[c] = (v.Vol + c * Ev)[vi] + Vb[c];
+    for (int c = 0; c < 5; ++c) V[c] = __builtin_nontemporal_load(v.Vol + c * Ev + vi) + Vb[c];
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -1582,10 +1583,10 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         double *dUc = v.dU + c * Ev;
         // the first stage (A = 0) does not read the register: whatever it
         // holds (a restored state, an aborted step) cannot leak into the step
-        const double du = (v.rkA != 0.0 ? v.rkA * dUc[vi] : 0.0) + v.dt * R[c];
-        dUc[vi] = du;
+        const double du = (v.rkA != 0.0 ? v.rkA * __builtin_nontemporal_load(dUc + vi) : 0.0) + v.dt * R[c];
+        __builtin_nontemporal_store(du, dUc + vi);
         Unew[c] = Uold[c] + v.rkB * du;
-        (v.U + c * Ev)[vi] = Unew[c];
+        __builtin_nontemporal_store(Unew[c], v.U + c * Ev + vi);
       }
     }
   }
@@ -1608,7 +1609,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         real t[5];
         face_state<n, LGL>(su, (f & 1) ? sb.lp : sb.lm, base, stride, f & 1, t);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
+        for (int c = 0; c < 5; ++c) __builtin_nontemporal_store(t[c], trn + c * Ef + fb + fn);
       }
     }
   }
