@@ -64,8 +64,15 @@ struct View {
   int alpha_smooth; // 1: raise alpha to half the largest face neighbour's indicator value
   int lgl;          // Gauss-Lobatto nodes: l(-1), l(+1) are unit vectors, l-hat vanishes off the end nodes
   int remap;        // XCD-contiguous block order (single solve)
+  int nt;           // streaming (non-temporal) loads and stores in the two sweeps: set when the
+                    // working set exceeds what the on-die caches could keep (kStreamBytes)
   real ind_a, ind_c, ind_s, alpha_min, alpha_max, ind_T; // indicator (ind_T precomputed threshold)
 };
+
+// workspace bytes above which the sweeps stream their single-use data past the
+// caches: MI355X's 256 MB Infinity Cache keeps smaller working sets between
+// sweeps, and plain accesses serve those better
+constexpr size_t kStreamBytes = size_t(384) << 20;
 
 // offsets (in elements of `real`) inside the basis block, for n = N+1
 struct BasisOffsets {

@@ -40,6 +40,19 @@
 
 namespace dg {
 
+// loads and stores of single-use streams: non-temporal when NT (the working
+// set exceeds the on-die caches), plain otherwise
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T x, T *p) {
+  if constexpr (NT) __builtin_nontemporal_store(x, p);
+  else *p = x;
+}
+
 __device__ __forceinline__ int vnode(int n, int i, int j, int k) { return i + n * (j + n * k); }
 
 template <int n>
@@ -425,7 +438,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
     real U[5], P[6];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      Uold[c] = __builtin_nontemporal_load(v.U + c * Ev + vi);
+      Uold[c] = (v.U + c * Ev)[vi];
       U[c] = to_real(Uold[c], c, v);
     }
     cons2prim(U, gam, rR, P, bg);
@@ -491,10 +504,10 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         double *dUc = v.dU + c * Ev;
         // the first stage (A = 0) does not read the register: whatever it
         // holds (a restored state, an aborted step) cannot leak into the step
-        const double du = (v.rkA != 0.0 ? v.rkA * __builtin_nontemporal_load(dUc + vi) : 0.0) + v.dt * R[c];
-        __builtin_nontemporal_store(du, dUc + vi);
+        const double du = (v.rkA != 0.0 ? v.rkA * dUc[vi] : 0.0) + v.dt * R[c];
+        dUc[vi] = du;
         Unew[c] = Uold[c] + v.rkB * du;
-        __builtin_nontemporal_store(Unew[c], v.U + c * Ev + vi);
+        (v.U + c * Ev)[vi] = Unew[c];
       }
     }
   }
@@ -515,7 +528,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         real t[5];
         prolong_state<n>(sm, (f & 1) ? sb.lp : sb.lm, base, stride, t);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) __builtin_nontemporal_store(t[c], trn + c * Ef + fb + fn);
+        for (int c = 0; c < 5; ++c) (trn + c * Ef)[fb + fn] = t[c];
       }
     }
   }
@@ -703,7 +716,7 @@ struct VolLds {
 // follow from them: p = rho R T, H = gamma R T/(gamma - 1) + |u|^2/2.
 // The viscous part keeps the weak form.
 // ---------------------------------------------------------------------------
-template <int N, typename real, bool SHOCK, bool LGL, bool SPLIT, bool SUTH, bool DIAG = false>
+template <int N, typename real, bool SHOCK, bool LGL, bool SPLIT, bool SUTH, bool DIAG = false, bool NT = false>
 __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (VolLds<N, real, SHOCK, SPLIT>::minw))
     k_volume(const View<real> *views, const int *blk_start, int nreq, View<real> single) {
   using S = Sz<N>;
@@ -761,7 +774,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
     for (int m = 0; m < npt; ++m)
 #pragma unroll
-      for (int c = 0; c < 5; ++c) U[m][c] = to_real(__builtin_nontemporal_load(v.U + c * Ev + vi + m * tpe), c, v);
+      for (int c = 0; c < 5; ++c) U[m][c] = to_real(ld<NT>(v.U + c * Ev + vi + m * tpe), c, v);
   }
   // Lift_FillFlux operands: both sides' U traces and this side's n shat at
   // the thread's face nodes.  With one node per thread they are fetched here,
@@ -816,7 +829,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     for (int m = 0; m < npt; ++m) {
       const int am = a + m * tpe;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + am] = __builtin_nontemporal_load(v.Ja + c * Ev + vi + m * tpe);
+      for (int c = 0; c < 9; ++c) sm[L::J + c * n3 + am] = ld<NT>(v.Ja + c * Ev + vi + m * tpe);
       real P[6];
       cons2prim(U[m], gam, rR, P, bg);
       sm[L::V + 0 * n3 + am] = P[1];
@@ -1173,7 +1186,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
           for (int s = 0; s < 5; ++s) H[s] += tmp[s] * nv[2];
 #pragma unroll
-          for (int s = 1; s < 5; ++s) __builtin_nontemporal_store(H[s], v.Hv + (s - 1) * Ef + fb + fn);
+          for (int s = 1; s < 5; ++s) st<NT>(H[s], v.Hv + (s - 1) * Ef + fb + fn);
         }
       }
     }
@@ -1288,7 +1301,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
     for (int m = 0; m < npt; ++m)
 #pragma unroll
       for (int c = 0; c < 5; ++c)
-        __builtin_nontemporal_store(SPLIT ? Vs[m][c] + Vi[m][c] : Vi[m][c], v.Vol + c * Ev + vi + m * tpe);
+        st<NT>(SPLIT ? Vs[m][c] + Vi[m][c] : Vi[m][c], v.Vol + c * Ev + vi + m * tpe);
   }
   if constexpr (DIAG) {
     // the element's dissipation sums in a fixed order (reproducible, no atomics)
@@ -1324,7 +1337,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 // pass; SH = 2 (the blend pass) adds the FV subcell operator, and with SPLIT
 // takes the split form's advective volume integral for the blend.
 // ---------------------------------------------------------------------------
-template <int N, typename real, int SH, bool LGL, bool SPLIT = false>
+template <int N, typename real, int SH, bool LGL, bool SPLIT = false, bool NT = false>
 __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk, const int mode) {
   using S = Sz<N>;
   constexpr int n = S::n, n2 = S::n2, n3 = S::n3, nf = S::nf, epb = S::epb;
@@ -1373,7 +1386,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
   if (active) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      Uold[c] = __builtin_nontemporal_load(v.U + c * Ev + vi);
+      Uold[c] = ld<NT>(v.U + c * Ev + vi);
       su[c * Pad<n>::size + pa] = to_real(Uold[c], c, v);
     }
   }
@@ -1548,7 +1561,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
   if (active) {
     real V[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) V[c] = __builtin_nontemporal_load(v.Vol + c * Ev + vi) + Vb[c];
+    for (int c = 0; c < 5; ++c) V[c] = ld<NT>(v.Vol + c * Ev + vi) + Vb[c];
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -1583,10 +1596,10 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         double *dUc = v.dU + c * Ev;
         // the first stage (A = 0) does not read the register: whatever it
         // holds (a restored state, an aborted step) cannot leak into the step
-        const double du = (v.rkA != 0.0 ? v.rkA * __builtin_nontemporal_load(dUc + vi) : 0.0) + v.dt * R[c];
-        __builtin_nontemporal_store(du, dUc + vi);
+        const double du = (v.rkA != 0.0 ? v.rkA * ld<NT>(dUc + vi) : 0.0) + v.dt * R[c];
+        st<NT>(du, dUc + vi);
         Unew[c] = Uold[c] + v.rkB * du;
-        __builtin_nontemporal_store(Unew[c], v.U + c * Ev + vi);
+        st<NT>(Unew[c], v.U + c * Ev + vi);
       }
     }
   }
@@ -1609,7 +1622,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         real t[5];
         face_state<n, LGL>(su, (f & 1) ? sb.lp : sb.lm, base, stride, f & 1, t);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) __builtin_nontemporal_store(t[c], trn + c * Ef + fb + fn);
+        for (int c = 0; c < 5; ++c) st<NT>(t[c], trn + c * Ef + fb + fn);
       }
     }
   }
@@ -1618,12 +1631,12 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
 
 // Surface sweep: SH = 0 without shock capturing; SH = 1 with it, for the
 // workgroups without a blended element (the others are listed for k_blend).
-template <int N, typename real, int SH, bool LGL>
+template <int N, typename real, int SH, bool LGL, bool NT>
 __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_surface(const View<real> *views, const int *blk_start,
                                                                           int nreq, View<real> single, int mode) {
   int lblk;
   const View<real> v = select_view(views, blk_start, nreq, single, lblk);
-  surface_body<N, real, SH, LGL>(v, lblk, mode);
+  surface_body<N, real, SH, LGL, false, NT>(v, lblk, mode);
 }
 
 // Blend pass: the surface sweep with the FV subcell blend, for the workgroups
@@ -1654,10 +1667,17 @@ template <int N, typename real, bool SHOCK, bool LGL, bool SPLIT>
 static void volume_sweep(dim3 grid, const View<real> *views, const int *blk_start, int nreq, const View<real> &v0,
                          hipStream_t st) {
   constexpr int threads = VolLds<N, real, SHOCK, SPLIT>::threads;
-  if (v0.visc_law)
-    k_volume<N, real, SHOCK, LGL, SPLIT, true><<<grid, threads, 0, st>>>(views, blk_start, nreq, v0);
-  else
-    k_volume<N, real, SHOCK, LGL, SPLIT, false><<<grid, threads, 0, st>>>(views, blk_start, nreq, v0);
+  if (v0.nt) {
+    if (v0.visc_law)
+      k_volume<N, real, SHOCK, LGL, SPLIT, true, false, true><<<grid, threads, 0, st>>>(views, blk_start, nreq, v0);
+    else
+      k_volume<N, real, SHOCK, LGL, SPLIT, false, false, true><<<grid, threads, 0, st>>>(views, blk_start, nreq, v0);
+  } else {
+    if (v0.visc_law)
+      k_volume<N, real, SHOCK, LGL, SPLIT, true><<<grid, threads, 0, st>>>(views, blk_start, nreq, v0);
+    else
+      k_volume<N, real, SHOCK, LGL, SPLIT, false><<<grid, threads, 0, st>>>(views, blk_start, nreq, v0);
+  }
 }
 
 template <int N, typename real, bool LGL>
@@ -1705,7 +1725,10 @@ static hipError_t launch_nl(Kernel k, int mode, const View<real> *views, const i
       // surface sweep (after a volume sweep), or the one-sweep Euler operator
       if (v0.shock) {
         if constexpr (N >= 2 && N <= 7) {  // the degrees shock capturing accepts
-          k_surface<N, real, 1, LGL><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          if (v0.nt)
+            k_surface<N, real, 1, LGL, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+          else
+            k_surface<N, real, 1, LGL, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
           if (v0.split) {
             if constexpr (LGL) {
               k_blend<N, real, LGL, true><<<std::min(blocks, kBlendBlocks), block, 0, st>>>(views, nreq, v0, mode);
@@ -1719,7 +1742,10 @@ static hipError_t launch_nl(Kernel k, int mode, const View<real> *views, const i
           return hipErrorInvalidValue;
         }
       } else if (v0.viscous || v0.split) {
-        k_surface<N, real, 0, LGL><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        if (v0.nt)
+          k_surface<N, real, 0, LGL, true><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
+        else
+          k_surface<N, real, 0, LGL, false><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       } else {
         k_rhs<N, real><<<grid, block, 0, st>>>(views, blk_start, nreq, v0, mode);
       }

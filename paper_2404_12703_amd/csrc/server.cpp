@@ -511,6 +511,7 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
   View<real> *views = (View<real> *)h;
   int *blk = (int *)(h + sv->max_active * view_bytes());
   int total = 0;
+  size_t gbytes = 0;
   for (size_t r = 0; r < grp.size(); ++r) {
     Request &q = *grp[r];
     View<real> v = view_of<real>(q);
@@ -526,6 +527,7 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
     views[r] = as_offsets(v, sv->arena);
     blk[r] = total;
     total += blocks_per_elements(N, q.E);
+    gbytes += q.L.total;
   }
   blk[grp.size()] = total;
   char *d = sv->arena + slot * sv->desc_stride;
@@ -533,6 +535,7 @@ dg_status launch_group(dg_server *sv, Kernel k, int N, const std::vector<Request
   // the argument view: the group's settings (shock capturing, viscosity) and the arena
   View<real> v0 = view_of<real>(*grp[0]);
   v0.base = sv->arena;
+  v0.nt = gbytes >= kStreamBytes;  // the group's working set decides, as for a single solve
   if (e == hipSuccess)
     e = launch<real>(k, N, 0, (const View<real> *)d, (const int *)(d + sv->max_active * view_bytes()), (int)grp.size(),
                      total, v0, st);

@@ -206,6 +206,7 @@ void fill_view(View<real> &v, void *base, const Layout &L, const dg_params &p, i
     const char *env = std::getenv("DG_XCD_REMAP");
     v.remap = env ? std::atoi(env) : 0;
   }
+  v.nt = L.total >= kStreamBytes;
   v.ind_a = (real)p.ind_a;
   v.ind_c = (real)p.ind_c;
   v.ind_s = (real)p.ind_s;
