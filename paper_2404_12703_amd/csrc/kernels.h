@@ -471,6 +471,13 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
   }
   double Unew[5] = {0, 0, 0, 0, 0};
   if (active) {
+    // 1/J and the RK register, loaded before the gather: their latency
+    // overlaps it, and the register's five loads precede its five stores
+    // (which the compiler could not move them across)
+    const real iJ = v.invJ[vi];
+    double dUo[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dUo[c] = (mode == 0 && v.rkA != 0.0) ? (v.dU + c * Ev)[vi] : 0.0;
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -481,7 +488,6 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
 #pragma unroll
       for (int c = 0; c < 5; ++c) V[c] += sS[le][c][f * n2 + pqf[d]] * lh;
     }
-    const real iJ = v.invJ[vi];
     double R[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) R[c] = (double)(-(V[c] * iJ));
@@ -504,7 +510,7 @@ __global__ void __launch_bounds__(Sz<N>::threads, Sz<N>::minw) k_rhs(const View<
         double *dUc = v.dU + c * Ev;
         // the first stage (A = 0) does not read the register: whatever it
         // holds (a restored state, an aborted step) cannot leak into the step
-        const double du = (v.rkA != 0.0 ? v.rkA * dUc[vi] : 0.0) + v.dt * R[c];
+        const double du = (v.rkA != 0.0 ? v.rkA * dUo[c] : 0.0) + v.dt * R[c];
         dUc[vi] = du;
         Unew[c] = Uold[c] + v.rkB * du;
         (v.U + c * Ev)[vi] = Unew[c];
@@ -776,14 +782,23 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
       for (int c = 0; c < 5; ++c) U[m][c] = to_real(ld<NT>(v.U + c * Ev + vi + m * tpe), c, v);
   }
+  // 1/J at this thread's nodes, fetched beside the state: its first use comes
+  // after the lifting sums, and a load issued there would stall the wave
+  real iJe[npt];
+  if (active && visc) {
+#pragma unroll
+    for (int m = 0; m < npt; ++m) iJe[m] = v.invJ[vi + m * tpe];
+  }
   // Lift_FillFlux operands: both sides' U traces and this side's n shat at
   // the thread's face nodes.  With one node per thread they are fetched here,
   // beside the state, which hides their latency behind the metric loads (the
   // split-form sweep 3.9% faster at N = 7); the column-pair sweep fetches
   // them where it uses them (1% faster so).
   real tUo[L::upt][L::fpu][5], tUn[L::upt][L::fpu][5], tNs[L::upt][L::fpu][3];
+  bool prim[L::upt][L::fpu];  // this side is the face's primary side (read with the traces)
   auto fetch_face = [&](int r, int u, int f, int fn, int pq) {
     const int2 c = v.conn[e * 6 + f];
+    prim[r][u] = (c.y >> 3) & 1;
     int pp, qq;
     orient_map(c.y & 7, pq % n, pq / n, N, pp, qq);
     const uint32_t io = fb + fn, in = (uint32_t)c.x * n2 + pp + n * qq;
@@ -1039,9 +1054,8 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
       }
 #pragma unroll
       for (int m = 0; m < npt; ++m) {
-        const real iJ = v.invJ[vi + m * tpe];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) g[m][c] = JG[m][c] * iJ;
+        for (int c = 0; c < 12; ++c) g[m][c] = JG[m][c] * iJe[m];
       }
     }
   }
@@ -1163,7 +1177,7 @@ __global__ void __launch_bounds__((VolLds<N, real, SHOCK, SPLIT>::threads), (Vol
 #pragma unroll
         for (int u = 0; u < L::fpu; ++u) {
           const int f = 2 * d + s0 + u, fn = f * n2 + pq;
-          const bool primary = (v.conn[e * 6 + f].y >> 3) & 1;
+          const bool primary = prim[r][u];
           real nsv[3];
 #pragma unroll
           for (int dd = 0; dd < 3; ++dd) {
@@ -1562,6 +1576,13 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
     real V[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) V[c] = ld<NT>(v.Vol + c * Ev + vi) + Vb[c];
+    // 1/J and the RK register, loaded with the volume integral: their latency
+    // overlaps the gather, and the register's five loads precede its five
+    // stores (which the compiler could not move them across)
+    const real iJ = v.invJ[vi];
+    double dUo[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dUo[c] = (mode == 0 && v.rkA != 0.0) ? ld<NT>(v.dU + c * Ev + vi) : 0.0;
     // SurfInt gather (one writer per entry) and ApplyJac
     const int pqf[3] = {j + n * k, i + n * k, i + n * j};
     const int lf[3] = {i, j, k};
@@ -1573,7 +1594,6 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
 #pragma unroll
       for (int c = 0; c < 5; ++c) V[c] += sS[le][c][f * n2 + pqf[d]] * lh;
     }
-    const real iJ = v.invJ[vi];
     double R[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) R[c] = (double)(-(V[c] * iJ));
@@ -1596,7 +1616,7 @@ __device__ __forceinline__ void surface_body(const View<real> &v, const int lblk
         double *dUc = v.dU + c * Ev;
         // the first stage (A = 0) does not read the register: whatever it
         // holds (a restored state, an aborted step) cannot leak into the step
-        const double du = (v.rkA != 0.0 ? v.rkA * ld<NT>(dUc + vi) : 0.0) + v.dt * R[c];
+        const double du = (v.rkA != 0.0 ? v.rkA * dUo[c] : 0.0) + v.dt * R[c];
         st<NT>(du, dUc + vi);
         Unew[c] = Uold[c] + v.rkB * du;
         st<NT>(Unew[c], v.U + c * Ev + vi);

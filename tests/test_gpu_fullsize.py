@@ -13,7 +13,8 @@ import pytest
 import oracle as O
 import workloads as W
 
-pytestmark = pytest.mark.gpu
+# the oracle's share takes minutes on a slow host; each chunk prints its progress
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 
 def rel(a, b):
